@@ -1,0 +1,178 @@
+/*
+ * pcms_mls.h -- C interface of the MI355X (gfx950) point-cloud field-transfer
+ * library: moving-least-squares ("local weighted polynomial fitting") mapping
+ * of fields from a source point cloud to a target point cloud.
+ *
+ * The operation is the one of the PCMS paper (Merson et al., "PCMS: Parallel
+ * Coupler For Multimodel Simulations"), Section 3.2.1, Eq. 1: for every
+ * target t_i, the sources selected by a radial cut-off (Section 3.2.1's
+ * selection function) are fitted by the weighted, Tikhonov-regularised
+ * least-squares polynomial of total degree <= p, and the fit is evaluated at
+ * t_i.  Sources are located with a uniform-grid search (Section 3.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer owned by the caller (for
+ *    example torch.Tensor.data_ptr()).  It must stay valid until the work
+ *    enqueued on `stream` has completed.  The library never frees caller
+ *    memory and keeps no caller pointer past the call.
+ *  - Opaque handles (pcms_grid) are owned by the library and released with
+ *    their *_free function.
+ *  - Points are [n][dim] float64 row-major, dim in 1..5.  Fields are
+ *    [n_fields][n] float64 (field-major).  Indices and per-target counts are
+ *    int32 (n_src < 2^31).  Coordinates must be finite.
+ *  - Every call enqueues on `stream` (NULL = the null stream).  Unless
+ *    PCMS_ASYNC is set, the call then waits for the stream and turns the
+ *    per-target statuses into its return code.
+ *  - Argument errors are detected on the host before any HIP call and
+ *    return PCMS_ERR_ARG.  No C++ exception crosses this interface.  The
+ *    last error message of the calling thread is pcms_last_error().
+ *
+ * Per-target status (uint8): 0 OK; 1 UNDERDETERMINED (fewer than m kept
+ * sources: the paper's error condition); 2 SINGULAR (a Cholesky pivot at or
+ * below 1e-13 * max diag of the moment matrix, or, in the mixed modes, an
+ * iterative-refinement correction larger than the solution); 3
+ * RADIUS_EXHAUSTED (growing radius ran out of doublings before reaching the
+ * minimum count); bit 0x10 CAPPED (more than k_cap sources were inside the
+ * radius; the k_cap nearest by (distance, source index) were kept).  Targets
+ * with status 1-3 get NaN outputs.
+ */
+#ifndef PCMS_MLS_H
+#define PCMS_MLS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *pcms_stream_t; /* a hipStream_t */
+
+typedef int32_t pcms_status;
+#define PCMS_OK 0
+#define PCMS_ERR_ARG 1              /* invalid argument, nothing was enqueued */
+#define PCMS_ERR_HIP 2              /* a HIP runtime call failed */
+#define PCMS_ERR_NOMEM 3            /* device allocation failed */
+#define PCMS_ERR_UNDERDETERMINED 4  /* at least one target was underdetermined */
+#define PCMS_ERR_SINGULAR 5         /* at least one target had a singular moment matrix */
+#define PCMS_ERR_RADIUS_EXHAUSTED 6 /* at least one growing radius ran out of doublings */
+
+#define PCMS_TGT_OK 0
+#define PCMS_TGT_UNDERDETERMINED 1
+#define PCMS_TGT_SINGULAR 2
+#define PCMS_TGT_RADIUS_EXHAUSTED 3
+#define PCMS_TGT_CAPPED 0x10
+
+#define PCMS_MAX_DIM 5
+#define PCMS_MAX_KCAP 256
+
+/* Radius selection (Section 3.2.1).  The distance is the metric
+ * D = sum_k ((t_k - s_k) * g_k)^2 evaluated in FP64 as a fused multiply-add
+ * chain in dimension order; a source is selected when D < r^2 (strictly).
+ *   FIXED: r is given.
+ *   GROW:  r starts at `r`; per target, r^2 doubles until at least `n_min`
+ *          sources are inside or `max_iter` doublings are spent (the paper's
+ *          "minimum number of source points and an initial radius").
+ *   KNN:   r^2 is the k-th smallest D over all sources, so k-1 sources lie
+ *          strictly inside (ties aside) and the k-th sits where the weight
+ *          vanishes. */
+#define PCMS_RADIUS_FIXED 0
+#define PCMS_RADIUS_KNN 1
+#define PCMS_RADIUS_GROW 2
+typedef struct {
+    int32_t mode;     /* PCMS_RADIUS_* */
+    int32_t k;        /* KNN order, 1 <= k <= n_src */
+    int32_t n_min;    /* GROW minimum count, >= 1 */
+    int32_t max_iter; /* GROW doublings, >= 0 (40 is a good default) */
+    double r;         /* FIXED radius / GROW initial radius, finite, > 0 */
+} pcms_radius;
+
+/* Radial weights phi(q), q = sqrt(D) / r (Table 1 of the paper, shape
+ * parameter a = 2, plus Wendland C2 (1-q)^4 (4q+1), the default). */
+#define PCMS_WEIGHT_WENDLAND_C2 0
+#define PCMS_WEIGHT_C4 1
+#define PCMS_WEIGHT_GAUSSIAN 2
+#define PCMS_WEIGHT_CONST 3
+#define PCMS_WEIGHT_IMQ 4
+
+/* Arithmetic of the moment assembly.
+ *   FP64:         everything in FP64.
+ *   MIXED:        weights and the moment matrix G = P^T W P in FP32 with FP32
+ *                 accumulation; Cholesky, solve and evaluation in FP64.
+ *   MIXED_REFINE: MIXED plus one FP64 iterative-refinement step of the
+ *                 shape functional G^{-1} e_0 (residual formed in FP64). */
+#define PCMS_FP64 0
+#define PCMS_MIXED 1
+#define PCMS_MIXED_REFINE 2
+
+#define PCMS_ASYNC 0x1u /* return after enqueue; statuses land in opts.summary */
+
+typedef struct {
+    int32_t weight;           /* PCMS_WEIGHT_* */
+    int32_t precision;        /* PCMS_FP64 / PCMS_MIXED / PCMS_MIXED_REFINE */
+    double lambda;            /* Tikhonov parameter of Eq. 1, >= 0, in the radius-scaled basis */
+    uint32_t flags;           /* PCMS_ASYNC */
+    int32_t block;            /* targets per workgroup: 0 = library choice, else 64/128/256 */
+    int32_t *summary;         /* device int32[4] or NULL: counts of statuses 1, 2, 3 and CAPPED */
+} pcms_mls_opts;
+
+/* Set opts to the defaults (Wendland C2, FP64, lambda 0, synchronous). */
+void pcms_mls_opts_default(pcms_mls_opts *opts);
+
+/* ---------------------------------------------------------------------- */
+/* Uniform grid (Section 3.3): sources sorted by bucket.                   */
+/* ---------------------------------------------------------------------- */
+typedef struct pcms_grid pcms_grid;
+
+/* Build a uniform grid over the sources.  The grid keeps its own sorted copy
+ * of the coordinates, so `src` may be freed once the stream has passed this
+ * call.  inv_scale: HOST float64[dim] metric factors g (NULL = all 1).
+ * cell_width: bucket width in metric units (> 0), or 0 to size buckets for
+ * about `pts_per_cell` sources each (pts_per_cell <= 0 picks 2^dim).
+ * Reusable across transfers of changing fields (the paper's case of a static
+ * discretisation queried many times). */
+pcms_status pcms_grid_build(const double *src, int64_t n_src, int32_t dim, const double *inv_scale,
+                            double cell_width, double pts_per_cell, pcms_stream_t stream,
+                            pcms_grid **out);
+pcms_status pcms_grid_free(pcms_grid *grid);
+
+/* Neighbour lists (Section 3.2.1 selection set, capped).  For target i:
+ * nbr[i*k_cap + e], e < n_kept[i], are the kept original source indices in
+ * ascending order (entries past n_kept are unspecified); n_found[i] is the
+ * count strictly inside the radius before the cap; r2[i] the squared radius;
+ * status[i] as above (UNDERDETERMINED is not judged here).  n_found, r2 and
+ * status may be NULL.  1 <= k_cap <= 256. */
+pcms_status pcms_neighbors(const pcms_grid *grid, const double *tgt, int64_t n_tgt,
+                           const pcms_radius *radius, int32_t k_cap, pcms_stream_t stream,
+                           int32_t *nbr, int32_t *n_kept, int32_t *n_found, double *r2,
+                           uint8_t *status);
+
+/* Field transfer (Section 3.2.1, Eq. 1), one shot: builds the grid, searches,
+ * fits and evaluates.  src_vals [n_fields][n_src]; tgt_vals [n_fields][n_tgt]
+ * receives the fitted values (NaN for failed targets); status [n_tgt] may be
+ * NULL.  basis_degree 0..2 (m = C(dim+degree, degree) monomials in
+ * target-centred, radius-scaled coordinates); m <= k_cap <= 256.
+ * inv_scale: HOST float64[dim] or NULL. */
+pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, const double *src_vals,
+                              int32_t n_fields, const double *tgt, int64_t n_tgt,
+                              int32_t basis_degree, const pcms_radius *radius, int32_t k_cap,
+                              const double *inv_scale, const pcms_mls_opts *opts,
+                              pcms_stream_t stream, double *tgt_vals, uint8_t *status);
+
+/* Same on a prebuilt grid (its metric and sorted sources are reused). */
+pcms_status pcms_mls_transfer_grid(const pcms_grid *grid, const double *src_vals, int32_t n_fields,
+                                   const double *tgt, int64_t n_tgt, int32_t basis_degree,
+                                   const pcms_radius *radius, int32_t k_cap,
+                                   const pcms_mls_opts *opts, pcms_stream_t stream,
+                                   double *tgt_vals, uint8_t *status);
+
+/* Library version (major*10000 + minor*100 + patch) and the calling
+ * thread's last error message ("" if none). */
+int32_t pcms_version(void);
+const char *pcms_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCMS_MLS_H */

@@ -1,0 +1,374 @@
+// C entry points: argument validation (host only, before any HIP call),
+// orchestration of the grid build, target ordering, search and fit kernels
+// on the caller's stream, and the status/return-code plumbing.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdlib.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+namespace pcms {
+
+namespace {
+thread_local std::string g_last_error;
+
+bool finite_pos(double x) { return x > 0.0 && std::isfinite(x); }
+
+int num_monomials(int dim, int degree)
+{
+    return degree == 0 ? 1 : degree == 1 ? 1 + dim : 1 + dim + dim * (dim + 1) / 2;
+}
+
+double unit_ball_volume(int d)
+{
+    return pow(M_PI, 0.5 * d) / tgamma(0.5 * d + 1.0);
+}
+
+pcms_status arg_error(const std::string &m)
+{
+    set_error(m);
+    return PCMS_ERR_ARG;
+}
+
+pcms_status check_radius(const pcms_radius *r, int64_t n_src)
+{
+    if (!r) return arg_error("radius is NULL");
+    if (r->mode == PCMS_RADIUS_FIXED) {
+        if (!finite_pos(r->r)) return arg_error("fixed radius must be finite and > 0");
+    } else if (r->mode == PCMS_RADIUS_GROW) {
+        if (!finite_pos(r->r)) return arg_error("initial radius must be finite and > 0");
+        if (r->n_min < 1) return arg_error("n_min must be >= 1");
+        if (r->max_iter < 0 || r->max_iter > 2000) return arg_error("max_iter must be in [0, 2000]");
+    } else if (r->mode == PCMS_RADIUS_KNN) {
+        if (r->k < 1 || (int64_t)r->k > n_src) return arg_error("KNN k must be in [1, n_src]");
+    } else {
+        return arg_error("unknown radius mode");
+    }
+    return PCMS_OK;
+}
+
+pcms_status check_scale(const double *g, int dim)
+{
+    if (!g) return PCMS_OK;
+    for (int k = 0; k < dim; ++k)
+        if (!finite_pos(g[k])) return arg_error("inv_scale entries must be finite and > 0");
+    return PCMS_OK;
+}
+
+pcms_status check_opts(const pcms_mls_opts *o)
+{
+    if (!o) return PCMS_OK;
+    if (o->weight < PCMS_WEIGHT_WENDLAND_C2 || o->weight > PCMS_WEIGHT_IMQ)
+        return arg_error("unknown weight function");
+    if (o->precision < PCMS_FP64 || o->precision > PCMS_MIXED_REFINE)
+        return arg_error("unknown precision");
+    if (!(o->lambda >= 0.0) || !std::isfinite(o->lambda)) return arg_error("lambda must be finite and >= 0");
+    if (o->block != 0 && o->block != 64 && o->block != 128 && o->block != 256)
+        return arg_error("block must be 0, 64, 128 or 256");
+    if ((o->flags & PCMS_ASYNC) && !o->summary)
+        return arg_error("PCMS_ASYNC needs a device summary buffer");
+    return PCMS_OK;
+}
+
+// Cell sizing for a one-shot call: buckets about one support radius wide.
+void cell_spec(const pcms_radius *r, int dim, double *cell_width, double *pts_per_cell)
+{
+    *cell_width = 0.0;
+    *pts_per_cell = 0.0;
+    const char *env = getenv("PCMS_CELL_FACTOR");
+    double cf = env ? atof(env) : 1.0;
+    if (!(cf > 0.0)) cf = 1.0;
+    if (r->mode == PCMS_RADIUS_KNN)
+        *pts_per_cell = pow(cf, dim) * r->k / unit_ball_volume(dim);
+    else
+        *cell_width = cf * r->r;
+}
+
+struct Scratch {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    ~Scratch()
+    {
+        if (p) scratch_free(p, s);
+    }
+};
+
+void grid_alloc_free(Grid *g)
+{
+    if (!g) return;
+    if (g->params) (void)hipFree(g->params);
+    if (g->cell_start) (void)hipFree(g->cell_start);
+    if (g->perm) (void)hipFree(g->perm);
+    if (g->spts) (void)hipFree(g->spts);
+    delete g;
+}
+
+// Statuses -> return code (synchronous mode).
+pcms_status finish(const int32_t *summary_dev, bool async, hipStream_t s, bool judge_underdet)
+{
+    if (async) return PCMS_OK;
+    int32_t h[4] = {0, 0, 0, 0};
+    PCMS_HIP(hipMemcpyAsync(h, summary_dev, sizeof(h), hipMemcpyDeviceToHost, s));
+    PCMS_HIP(hipStreamSynchronize(s));
+    if (judge_underdet && h[0] > 0) {
+        set_error(std::to_string(h[0]) + " target(s) underdetermined");
+        return PCMS_ERR_UNDERDETERMINED;
+    }
+    if (h[1] > 0) {
+        set_error(std::to_string(h[1]) + " target(s) with a singular moment matrix");
+        return PCMS_ERR_SINGULAR;
+    }
+    if (h[2] > 0) {
+        set_error(std::to_string(h[2]) + " target(s) ran out of radius doublings");
+        return PCMS_ERR_RADIUS_EXHAUSTED;
+    }
+    return PCMS_OK;
+}
+
+std::once_flag g_pool_once[64];
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+pcms_status hip_fail(hipError_t e, const char *what)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? PCMS_ERR_NOMEM : PCMS_ERR_HIP;
+}
+
+pcms_status scratch_alloc(void **p, size_t bytes, hipStream_t s)
+{
+    int dev = 0;
+    PCMS_HIP(hipGetDevice(&dev));
+    if (dev >= 0 && dev < 64) {
+        std::call_once(g_pool_once[dev], [dev]() {
+            hipMemPool_t pool;
+            if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+                uint64_t keep = UINT64_MAX;   // keep freed blocks cached in the pool
+                (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+            }
+        });
+    }
+    hipError_t e = hipMallocAsync(p, bytes > 0 ? bytes : 256, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
+    return PCMS_OK;
+}
+
+void scratch_free(void *p, hipStream_t s)
+{
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+}  // namespace pcms
+
+using namespace pcms;
+
+extern "C" {
+
+void pcms_mls_opts_default(pcms_mls_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->weight = PCMS_WEIGHT_WENDLAND_C2;
+    o->precision = PCMS_FP64;
+    o->lambda = 0.0;
+}
+
+int32_t pcms_version(void) { return 100; }
+
+const char *pcms_last_error(void) { return g_last_error.c_str(); }
+
+static pcms_status grid_create(int64_t n_src, int32_t dim, const double *inv_scale, Grid **out)
+{
+    Grid *g = new (std::nothrow) Grid();
+    if (!g) return PCMS_ERR_NOMEM;
+    g->dim = dim;
+    g->n_src = n_src;
+    g->n_cells_cap = cells_cap_for(n_src);
+    for (int k = 0; k < kMaxDim; ++k) g->g[k] = (inv_scale && k < dim) ? inv_scale[k] : 1.0;
+    hipError_t e;
+    if ((e = hipGetDevice(&g->device)) != hipSuccess ||
+        (e = hipMalloc(&g->params, sizeof(GridParams))) != hipSuccess ||
+        (e = hipMalloc(&g->cell_start, sizeof(int) * ((size_t)g->n_cells_cap + 1))) != hipSuccess ||
+        (e = hipMalloc(&g->perm, sizeof(int) * (size_t)n_src)) != hipSuccess ||
+        (e = hipMalloc(&g->spts, sizeof(double) * (size_t)n_src * dim)) != hipSuccess) {
+        grid_alloc_free(g);
+        return hip_fail(e, "hipMalloc(grid)");
+    }
+    *out = g;
+    return PCMS_OK;
+}
+
+pcms_status pcms_grid_build(const double *src, int64_t n_src, int32_t dim, const double *inv_scale,
+                            double cell_width, double pts_per_cell, pcms_stream_t stream,
+                            pcms_grid **out)
+{
+    if (!out) return arg_error("out is NULL");
+    *out = nullptr;
+    if (dim < 1 || dim > kMaxDim) return arg_error("dim must be in [1, 5]");
+    if (n_src < 1 || n_src >= ((int64_t)1 << 31) / 2) return arg_error("n_src must be in [1, 2^30)");
+    if (!src) return arg_error("src is NULL");
+    if (!(cell_width >= 0.0) || !std::isfinite(cell_width)) return arg_error("cell_width must be finite and >= 0");
+    if (!std::isfinite(pts_per_cell)) return arg_error("pts_per_cell must be finite");
+    pcms_status st = check_scale(inv_scale, dim);
+    if (st != PCMS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Grid *g = nullptr;
+    st = grid_create(n_src, dim, inv_scale, &g);
+    if (st != PCMS_OK) return st;
+    st = build_grid_device(g, src, cell_width, pts_per_cell, s);
+    if (st != PCMS_OK) {
+        grid_alloc_free(g);
+        return st;
+    }
+    *out = reinterpret_cast<pcms_grid *>(g);
+    return PCMS_OK;
+}
+
+pcms_status pcms_grid_free(pcms_grid *grid)
+{
+    if (!grid) return PCMS_OK;
+    Grid *g = reinterpret_cast<Grid *>(grid);
+    (void)hipDeviceSynchronize();
+    grid_alloc_free(g);
+    return PCMS_OK;
+}
+
+pcms_status pcms_neighbors(const pcms_grid *grid, const double *tgt, int64_t n_tgt,
+                           const pcms_radius *radius, int32_t k_cap, pcms_stream_t stream,
+                           int32_t *nbr, int32_t *n_kept, int32_t *n_found, double *r2,
+                           uint8_t *status)
+{
+    if (!grid) return arg_error("grid is NULL");
+    const Grid *g = reinterpret_cast<const Grid *>(grid);
+    if (n_tgt < 0 || n_tgt >= ((int64_t)1 << 31) / 2) return arg_error("n_tgt must be in [0, 2^30)");
+    if (k_cap < 1 || k_cap > kMaxKcap) return arg_error("k_cap must be in [1, 256]");
+    pcms_status st = check_radius(radius, g->n_src);
+    if (st != PCMS_OK) return st;
+    if (n_tgt > 0 && (!tgt || !nbr || !n_kept)) return arg_error("tgt, nbr and n_kept are required");
+    if (n_tgt == 0) return PCMS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc;
+    sc.s = s;
+    st = scratch_alloc(&sc.p, sizeof(int) * (size_t)n_tgt + 64, s);
+    if (st != PCMS_OK) return st;
+    int32_t *summary = (int32_t *)sc.p;
+    int *tperm = (int *)((char *)sc.p + 64);
+    if ((st = zero_ints(summary, 4, s)) != PCMS_OK) return st;
+    if ((st = sort_targets(g, tgt, n_tgt, tperm, s)) != PCMS_OK) return st;
+    LaunchSpec ls{g, tgt, tperm, n_tgt, *radius, k_cap, 0, summary};
+    if ((st = launch_neighbors(ls, nbr, n_kept, n_found, r2, status, s)) != PCMS_OK) return st;
+    return finish(summary, false, s, false);
+}
+
+static pcms_status transfer_common(const Grid *g, const double *src_vals, int32_t n_fields,
+                                   const double *tgt, int64_t n_tgt, int32_t degree,
+                                   const pcms_radius *radius, int32_t k_cap,
+                                   const pcms_mls_opts *opts, hipStream_t s, double *tgt_vals,
+                                   uint8_t *status)
+{
+    pcms_mls_opts o;
+    pcms_mls_opts_default(&o);
+    if (opts) o = *opts;
+    const bool async = (o.flags & PCMS_ASYNC) != 0;
+    Scratch sc;
+    sc.s = s;
+    size_t off_tperm = 64;
+    size_t off_svals = off_tperm + ((sizeof(int) * (size_t)n_tgt + 255) & ~(size_t)255);
+    size_t bytes = off_svals + sizeof(double) * (size_t)g->n_src * n_fields;
+    pcms_status st = scratch_alloc(&sc.p, bytes, s);
+    if (st != PCMS_OK) return st;
+    int32_t *summary = async ? o.summary : (int32_t *)sc.p;
+    int *tperm = (int *)((char *)sc.p + off_tperm);
+    double *svals = (double *)((char *)sc.p + off_svals);
+    if ((st = zero_ints(summary, 4, s)) != PCMS_OK) return st;
+    if ((st = sort_targets(g, tgt, n_tgt, tperm, s)) != PCMS_OK) return st;
+    if ((st = gather_values(g, src_vals, n_fields, svals, s)) != PCMS_OK) return st;
+    LaunchSpec ls{g, tgt, tperm, n_tgt, *radius, k_cap, o.block, summary};
+    st = launch_transfer(ls, svals, n_fields, degree, o.weight, o.precision, o.lambda, tgt_vals,
+                         status, s);
+    if (st != PCMS_OK) return st;
+    return finish(summary, async, s, true);
+}
+
+static pcms_status check_transfer_args(int64_t n_src, int32_t dim, const double *src_vals,
+                                       int32_t n_fields, const double *tgt, int64_t n_tgt,
+                                       int32_t degree, const pcms_radius *radius, int32_t k_cap,
+                                       const pcms_mls_opts *opts, double *tgt_vals)
+{
+    if (dim < 1 || dim > kMaxDim) return arg_error("dim must be in [1, 5]");
+    if (degree < 0 || degree > 2) return arg_error("basis_degree must be in [0, 2]");
+    if (n_fields < 1) return arg_error("n_fields must be >= 1");
+    if (n_tgt < 0 || n_tgt >= ((int64_t)1 << 31) / 2) return arg_error("n_tgt must be in [0, 2^30)");
+    const int m = num_monomials(dim, degree);
+    if (k_cap < m || k_cap > kMaxKcap) return arg_error("k_cap must be in [m, 256]");
+    pcms_status st = check_radius(radius, n_src);
+    if (st != PCMS_OK) return st;
+    if ((st = check_opts(opts)) != PCMS_OK) return st;
+    if (n_tgt > 0 && (!src_vals || !tgt || !tgt_vals)) return arg_error("src_vals, tgt and tgt_vals are required");
+    return PCMS_OK;
+}
+
+pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, const double *src_vals,
+                              int32_t n_fields, const double *tgt, int64_t n_tgt,
+                              int32_t basis_degree, const pcms_radius *radius, int32_t k_cap,
+                              const double *inv_scale, const pcms_mls_opts *opts,
+                              pcms_stream_t stream, double *tgt_vals, uint8_t *status)
+{
+    if (n_src < 1 || n_src >= ((int64_t)1 << 31) / 2) return arg_error("n_src must be in [1, 2^30)");
+    if (!src) return arg_error("src is NULL");
+    pcms_status st = check_transfer_args(n_src, dim, src_vals, n_fields, tgt, n_tgt, basis_degree,
+                                         radius, k_cap, opts, tgt_vals);
+    if (st != PCMS_OK) return st;
+    if ((st = check_scale(inv_scale, dim)) != PCMS_OK) return st;
+    if (n_tgt == 0) return PCMS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double cw, ppc;
+    cell_spec(radius, dim, &cw, &ppc);
+    // one-shot grid in stream-ordered scratch
+    Grid g{};
+    g.dim = dim;
+    g.n_src = n_src;
+    g.n_cells_cap = cells_cap_for(n_src);
+    for (int k = 0; k < kMaxDim; ++k) g.g[k] = (inv_scale && k < dim) ? inv_scale[k] : 1.0;
+    PCMS_HIP(hipGetDevice(&g.device));
+    Scratch sc;
+    sc.s = s;
+    size_t o_cs = 256;
+    size_t o_perm = o_cs + ((sizeof(int) * ((size_t)g.n_cells_cap + 1) + 255) & ~(size_t)255);
+    size_t o_spts = o_perm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
+    size_t bytes = o_spts + sizeof(double) * (size_t)n_src * dim;
+    if ((st = scratch_alloc(&sc.p, bytes, s)) != PCMS_OK) return st;
+    g.params = (GridParams *)sc.p;
+    g.cell_start = (int *)((char *)sc.p + o_cs);
+    g.perm = (int *)((char *)sc.p + o_perm);
+    g.spts = (double *)((char *)sc.p + o_spts);
+    if ((st = build_grid_device(&g, src, cw, ppc, s)) != PCMS_OK) return st;
+    return transfer_common(&g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts, s,
+                           tgt_vals, status);
+}
+
+pcms_status pcms_mls_transfer_grid(const pcms_grid *grid, const double *src_vals, int32_t n_fields,
+                                   const double *tgt, int64_t n_tgt, int32_t basis_degree,
+                                   const pcms_radius *radius, int32_t k_cap,
+                                   const pcms_mls_opts *opts, pcms_stream_t stream,
+                                   double *tgt_vals, uint8_t *status)
+{
+    if (!grid) return arg_error("grid is NULL");
+    const Grid *g = reinterpret_cast<const Grid *>(grid);
+    pcms_status st = check_transfer_args(g->n_src, g->dim, src_vals, n_fields, tgt, n_tgt,
+                                         basis_degree, radius, k_cap, opts, tgt_vals);
+    if (st != PCMS_OK) return st;
+    if (n_tgt == 0) return PCMS_OK;
+    return transfer_common(g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts,
+                           (hipStream_t)stream, tgt_vals, status);
+}
+
+}  // extern "C"

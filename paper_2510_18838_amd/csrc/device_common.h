@@ -1,0 +1,177 @@
+// Declarations shared by the kernels and their host emulation build.
+//
+// Everything here is plain arithmetic on plain pointers, marked host+device,
+// so the same code runs inside the HIP kernels and in the CPU emulation that
+// the test-suite builds with address sanitising to check indexing.
+#pragma once
+
+#include <stdint.h>
+
+#ifdef PCMS_HOST_EMULATION
+#include <algorithm>
+#include <cmath>
+#define PCMS_HD
+#define PCMS_INLINE inline
+using std::exp;
+using std::fabs;
+using std::floor;
+using std::fmax;
+using std::fmin;
+using std::isinf;
+using std::isnan;
+using std::max;
+using std::min;
+using std::nextafter;
+using std::pow;
+using std::sqrt;
+// Called by the emulation build when a lane addresses LDS words outside its own.
+[[noreturn]] void pcms_emu_lds_fault(int e, int words);
+#else
+#include <hip/hip_runtime.h>
+#define PCMS_HD __host__ __device__
+#define PCMS_INLINE __forceinline__
+#endif
+
+#include "pcms_mls.h"
+
+namespace pcms {
+
+constexpr int kMaxDim = PCMS_MAX_DIM;
+constexpr int kMaxKcap = PCMS_MAX_KCAP;
+
+// Device-resident description of a uniform grid.  Bucket coordinates of a
+// point x are c_k = clamp(floor((x_k - lo_k) * inv_w_k), 0, n_k - 1); the
+// linear bucket id is row-major with dimension 0 fastest, so the buckets of
+// one "row" (fixed c_1..c_{d-1}) are contiguous in sorted order.
+struct GridParams {
+    int dim;
+    int n_cells;
+    int n[kMaxDim];
+    int stride[kMaxDim];
+    double lo[kMaxDim];
+    double w[kMaxDim];      // bucket width, raw coordinates
+    double inv_w[kMaxDim];  // 1 / w
+    double g[kMaxDim];      // metric factors
+    double density;         // sources per unit metric volume of the bounding box
+};
+
+PCMS_HD PCMS_INLINE int bucket_of(const GridParams &p, int k, double x)
+{
+    double f = floor((x - p.lo[k]) * p.inv_w[k]);
+    f = fmax(f, 0.0);                     // also maps NaN to 0
+    f = fmin(f, (double)(p.n[k] - 1));
+    return (int)f;
+}
+
+// Bucket sizing from the bounding box [lo, hi]: width cell_width (metric
+// units) if > 0, else sized for about pts_per_cell sources per bucket; the
+// width grows until the bucket count fits `cap`.
+PCMS_HD inline void grid_params_compute(const double *lo, const double *hi, int dim, int64_t n,
+                                        const double *g, double cell_width, double pts_per_cell,
+                                        int cap, GridParams *out)
+{
+    GridParams p;
+    p.dim = dim;
+    double ext[kMaxDim];
+    double vol = 1.0;
+    int d_eff = 0;
+    for (int k = 0; k < kMaxDim; ++k) {
+        p.lo[k] = 0.0;
+        p.g[k] = 1.0;
+        p.n[k] = 1;
+        p.w[k] = 1.0;
+        p.inv_w[k] = 1.0;
+        p.stride[k] = 0;
+        ext[k] = 0.0;
+    }
+    for (int k = 0; k < dim; ++k) {
+        p.g[k] = g[k];
+        double l = lo[k], h = hi[k];
+        if (!(l <= h)) {
+            l = 0.0;
+            h = 0.0;
+        }
+        p.lo[k] = l;
+        ext[k] = (h - l) * p.g[k];
+        if (ext[k] > 0.0) {
+            vol *= ext[k];
+            d_eff++;
+        }
+    }
+    double wm;
+    if (cell_width > 0.0) {
+        wm = cell_width;
+    } else {
+        double ppc = pts_per_cell > 0.0 ? pts_per_cell : (double)(1 << dim);
+        wm = d_eff > 0 ? pow(ppc * vol / (double)(n > 0 ? n : 1), 1.0 / d_eff) : 1.0;
+        if (!(wm > 0.0) || !(wm < INFINITY)) wm = 1.0;
+    }
+    double total = 1.0;
+    for (int it = 0; it < 4000; ++it) {
+        total = 1.0;
+        for (int k = 0; k < dim; ++k) {
+            if (ext[k] > 0.0) {
+                double nk = floor(ext[k] / wm) + 1.0;
+                nk = fmin(nk, 1073741824.0);
+                p.n[k] = (int)nk;
+                p.w[k] = wm / p.g[k];
+            } else {
+                p.n[k] = 1;
+                p.w[k] = 1.0 / p.g[k];
+            }
+            p.inv_w[k] = 1.0 / p.w[k];
+            total *= (double)p.n[k];
+        }
+        if (total <= (double)cap) break;
+        wm *= 1.25;
+    }
+    if (total > (double)cap) {      // never exceed the allocated bucket count
+        for (int k = 0; k < dim; ++k) {
+            p.n[k] = 1;
+            p.w[k] = (ext[k] > 0.0 ? 2.0 * ext[k] : 1.0) / p.g[k];
+            p.inv_w[k] = 1.0 / p.w[k];
+        }
+    }
+    int s = 1;
+    for (int k = 0; k < dim; ++k) {
+        p.stride[k] = s;
+        s *= p.n[k];
+    }
+    p.n_cells = s;
+    p.density = d_eff > 0 ? (double)n / vol : 0.0;
+    *out = p;
+}
+
+PCMS_HD PCMS_INLINE unsigned bucket_key(const GridParams &p, const double *x)
+{
+    int id = 0;
+    for (int k = 0; k < p.dim; ++k) id += bucket_of(p, k, x[k]) * p.stride[k];
+    return (unsigned)id;
+}
+
+// --- pieces of the stable radix-sort scatter (one 8-bit digit per pass) ------
+// Lanes of one wave holding the same digit: AND of the per-bit ballots.
+PCMS_HD PCMS_INLINE unsigned long long digit_match(unsigned long long valid,
+                                                   const unsigned long long (&bits)[8], int digit)
+{
+    unsigned long long mask = valid;
+    for (int b = 0; b < 8; ++b) mask &= ((digit >> b) & 1) ? bits[b] : ~bits[b];
+    return mask;
+}
+
+PCMS_HD PCMS_INLINE unsigned long long lanes_below(int lane)
+{
+    return lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+// Output slot of an item: block running offset of its digit, plus the items
+// of the same digit in earlier waves of this round, plus earlier lanes.
+PCMS_HD PCMS_INLINE int scatter_slot(int running, const int (&wave_cnt)[4][256], int w, int digit,
+                                     unsigned long long mask, int lane)
+{
+    int pos = running + __builtin_popcountll(mask & lanes_below(lane));
+    for (int v = 0; v < w; ++v) pos += wave_cnt[v][digit];
+    return pos;
+}
+
+}  // namespace pcms

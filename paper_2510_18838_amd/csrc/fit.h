@@ -1,0 +1,389 @@
+// Per-target work of the neighbour-list and field-transfer kernels, written
+// as host+device functions of (arguments, target slot, LDS block, lane) so
+// the CPU emulation build runs exactly this code.
+//
+// Field transfer (PCMS paper, Section 3.2.1, Eq. 1): for target t with kept
+// sources s_e, weights w_e = phi(q_e), q_e = sqrt(D_e) / r, and monomials
+// p_e = p(xi_e) of total degree <= P in xi_e = (s_e - t) * g / r, the fitted
+// value is fhat = e_0^T G^{-1} B with G = sum_e w_e p_e p_e^T + lambda I and
+// B = sum_e w_e p_e f_e^T.  It is evaluated in shape-function form: one
+// Cholesky factorisation of G, one solve y = G^{-1} e_0, then
+// fhat_l = sum_e (w_e p_e . y) f_e,l for every field l, which shares the
+// factorisation across all fields.
+//
+// Precision: FP64 assembles G in FP64.  MIXED forms xi_e and w_e in FP32 and
+// accumulates G in FP32; the factorisation and everything after it are FP64.
+// MIXED_REFINE adds FP64 iterative refinement y += G^{-1}(e_0 - G y) with the
+// residual formed in FP64 from the same per-neighbour data (one step unless
+// the target is ill-conditioned).  In the mixed modes with lambda = 0 field
+// values are centred on the first kept neighbour's value.
+#pragma once
+
+#include <type_traits>
+
+#include "device_common.h"
+#include "search.h"
+
+namespace pcms {
+
+constexpr int kFieldChunk = 8;
+constexpr int kMaxRefine = 4;
+
+template <int D, int P>
+struct Basis {
+    static constexpr int M = P == 0 ? 1 : P == 1 ? 1 + D : 1 + D + D * (D + 1) / 2;
+    static constexpr int MM = M * (M + 1) / 2;
+};
+
+// Monomials of total degree <= P in graded-lex order:
+// 1; x_0 .. x_{D-1}; x_a x_b for a <= b, lexicographic in (a, b).
+template <int D, int P, typename T>
+PCMS_HD PCMS_INLINE void monomials(const T (&xi)[D], T (&p)[Basis<D, P>::M])
+{
+    int m = 0;
+    p[m++] = T(1);
+    if (P >= 1) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) p[m++] = xi[a];
+    }
+    if (P >= 2) {
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a; b < D; ++b) p[m++] = xi[a] * xi[b];
+    }
+}
+
+// Radial weights of q = r / r_c (Table 1, a = 2; Wendland C2 is the default).
+template <typename T>
+PCMS_HD PCMS_INLINE T weight_of(int kind, T q)
+{
+    if (!(q < T(1))) return T(0);
+    switch (kind) {
+    case PCMS_WEIGHT_C4: {
+        T o = T(1) - q;
+        T o2 = o * o;
+        T o6 = o2 * o2 * o2;
+        T poly = ((((T(5) * q + T(30)) * q + T(72)) * q + T(82)) * q + T(36)) * q + T(6);
+        return poly * o6;
+    }
+    case PCMS_WEIGHT_GAUSSIAN: return exp(-(T(2) * q) * (T(2) * q));
+    case PCMS_WEIGHT_CONST: return T(1);
+    case PCMS_WEIGHT_IMQ: return T(1) / sqrt(T(1) + (T(2) * q) * (T(2) * q));
+    default: {
+        T o = T(1) - q;
+        T o2 = o * o;
+        return o2 * o2 * (T(4) * q + T(1));
+    }
+    }
+}
+
+// Packed upper-triangular index of (a, b), a <= b.
+template <int M>
+PCMS_HD PCMS_INLINE constexpr int tri(int a, int b)
+{
+    return a * M - a * (a - 1) / 2 + (b - a);
+}
+
+// In-place Cholesky of the packed SPD matrix A (upper triangle rows),
+// overwriting it with the factor R = L^T (A = R^T R).  Returns false when a
+// pivot is not above 1e-13 * max diag(A).
+template <int M>
+PCMS_HD PCMS_INLINE bool cholesky(double (&A)[M * (M + 1) / 2], double (&inv_diag)[M])
+{
+    double maxd = 0.0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) maxd = fmax(maxd, A[tri<M>(i, i)]);
+    const double tau = 1e-13 * maxd;
+    bool ok = maxd > 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        double s = A[tri<M>(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s = __builtin_fma(-A[tri<M>(k, j)], A[tri<M>(k, j)], s);
+        ok = ok && (s > tau);
+        double d = sqrt(fmax(s, 1e-300));
+        double id = 1.0 / d;
+        A[tri<M>(j, j)] = d;
+        inv_diag[j] = id;
+#pragma unroll
+        for (int i = j + 1; i < M; ++i) {
+            double x = A[tri<M>(j, i)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) x = __builtin_fma(-A[tri<M>(k, j)], A[tri<M>(k, i)], x);
+            A[tri<M>(j, i)] = x * id;
+        }
+    }
+    return ok;
+}
+
+// Solves R^T R x = b in place with the packed factor R.
+template <int M>
+PCMS_HD PCMS_INLINE void chol_solve(const double (&R)[M * (M + 1) / 2],
+                                    const double (&inv_diag)[M], double (&x)[M])
+{
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        double s = x[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s = __builtin_fma(-R[tri<M>(k, i)], x[k], s);
+        x[i] = s * inv_diag[i];
+    }
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
+        double s = x[i];
+#pragma unroll
+        for (int k = i + 1; k < M; ++k) s = __builtin_fma(-R[tri<M>(i, k)], x[k], s);
+        x[i] = s * inv_diag[i];
+    }
+}
+
+struct KArgs {
+    const GridParams *gp;
+    const int *cs;
+    const double *spts;
+    const int *perm;
+    const double *tgt;
+    const int *tperm;
+    int n_tgt;
+    int mode;
+    int k;
+    int n_min;
+    int max_iter;
+    double r;
+    int k_cap;
+    int words;             // LDS words per lane
+    int n_blocks;          // logical blocks (before XCD padding)
+    // transfer only
+    const double *svals;   // [n_src][nf], sorted order
+    int nf;
+    int weight;
+    int refine;
+    double lambda;
+    double *out;           // [nf][n_tgt]
+    // outputs
+    int32_t *nbr;
+    int32_t *n_kept;
+    int32_t *n_found;
+    double *r2;
+    uint8_t *status;
+    int32_t *summary;
+};
+
+// Radius and kept list for one target; returns the status bits, the count
+// inside the radius, the number of kept list entries and r^2.
+template <int D, bool UNIT>
+PCMS_HD PCMS_INLINE int select_target(LaneSearch<D, UNIT> &S, const KArgs &a, int &n_found,
+                                      int &n_kept, double &r2)
+{
+    int st = PCMS_TGT_OK;
+    if (a.mode == PCMS_RADIUS_FIXED) {
+        r2 = a.r * a.r;
+        n_found = S.collect(r2);
+    } else if (a.mode == PCMS_RADIUS_GROW) {
+        r2 = a.r * a.r;
+        n_found = S.collect(r2);
+        int it = 0;
+        while (n_found < a.n_min && it < a.max_iter) {
+            r2 = 2.0 * r2;
+            ++it;
+            n_found = S.collect(r2);
+        }
+        if (n_found < a.n_min) st = PCMS_TGT_RADIUS_EXHAUSTED;
+    } else {
+        double guess = S.knn_radius_guess(a.k) * 1.25;
+        r2 = S.kth(a.k, 0.0, 0, guess * guess, S.words / 2);
+        n_found = S.collect(r2);
+    }
+    n_kept = min(n_found, a.k_cap);
+    if (n_found > a.k_cap) {
+        st |= PCMS_TGT_CAPPED;
+        n_kept = S.cap_collect(r2);
+    }
+    return st;
+}
+
+template <int D>
+PCMS_HD PCMS_INLINE void load_point(const double *__restrict__ x, int i, double (&t)[D])
+{
+#pragma unroll
+    for (int k = 0; k < D; ++k) t[k] = x[(size_t)i * D + k];
+}
+
+// Neighbour list of the target at sorted slot i (original indices, ascending).
+template <int D, bool UNIT>
+PCMS_HD PCMS_INLINE int nbr_target(const KArgs &a, const GridParams &gp, int i, int *lds, int lane,
+                                   int ls)
+{
+    const int ti = a.tperm[i];
+    LaneSearch<D, UNIT> S{gp, a.cs, a.spts, a.perm, {}, lds, lane, ls, a.k_cap, a.words};
+    load_point<D>(a.tgt, ti, S.t);
+    int n_found, n;
+    double r2;
+    const int st = select_target<D, UNIT>(S, a, n_found, n, r2);
+    for (int e = 0; e < n; ++e) S.at(e) = a.perm[S.at(e)];
+    for (int e = 1; e < n; ++e) {
+        int x = S.at(e);
+        int j = e - 1;
+        while (j >= 0 && S.at(j) > x) {
+            S.at(j + 1) = S.at(j);
+            --j;
+        }
+        S.at(j + 1) = x;
+    }
+    int32_t *row = a.nbr + (size_t)ti * a.k_cap;
+    for (int e = 0; e < n; ++e) row[e] = S.at(e);
+    a.n_kept[ti] = n;
+    if (a.n_found) a.n_found[ti] = n_found;
+    if (a.r2) a.r2[ti] = r2;
+    if (a.status) a.status[ti] = (uint8_t)st;
+    return st;
+}
+
+// Per-neighbour local data: monomials p and weight w, in T.
+template <int D, int P, bool UNIT, typename T>
+PCMS_HD PCMS_INLINE void neighbour_data(const GridParams &gp, const double (&t)[D],
+                                        const double *__restrict__ s, double inv_h, double inv_r2,
+                                        int weight, T (&p)[Basis<D, P>::M], T &w)
+{
+    double d2;
+    T xi[D];
+    {
+        double u = UNIT ? (t[0] - s[0]) : (t[0] - s[0]) * gp.g[0];
+        d2 = u * u;
+        xi[0] = (T)(-u * inv_h);
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            u = UNIT ? (t[k] - s[k]) : (t[k] - s[k]) * gp.g[k];
+            d2 = __builtin_fma(u, u, d2);
+            xi[k] = (T)(-u * inv_h);
+        }
+    }
+    T q = sqrt((T)(d2 * inv_r2));
+    w = weight_of<T>(weight, q);
+    monomials<D, P, T>(xi, p);
+}
+
+// Field transfer of the target at sorted slot i; returns its status.
+template <int D, int P, bool MIXED, bool UNIT>
+PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i, int *lds,
+                                    int lane, int ls)
+{
+    constexpr int M = Basis<D, P>::M;
+    constexpr int MM = Basis<D, P>::MM;
+    using TA = typename std::conditional<MIXED, float, double>::type;   // assembly type
+    const int ti = a.tperm[i];
+    LaneSearch<D, UNIT> S{gp, a.cs, a.spts, a.perm, {}, lds, lane, ls, a.k_cap, a.words};
+    load_point<D>(a.tgt, ti, S.t);
+    int n_found, n;
+    double r2;
+    int st = select_target<D, UNIT>(S, a, n_found, n, r2);
+    if ((st & 0xF) == PCMS_TGT_OK && n < M) st |= PCMS_TGT_UNDERDETERMINED;
+    double y[M];
+    double idg[M];
+    double R[MM];
+    if ((st & 0xF) == PCMS_TGT_OK) {
+        const double inv_h = 1.0 / sqrt(r2);
+        const double inv_r2 = 1.0 / r2;
+        // moment matrix G = sum w p p^T (upper triangle)
+        {
+            TA G[MM];
+#pragma unroll
+            for (int j = 0; j < MM; ++j) G[j] = TA(0);
+            for (int e = 0; e < n; ++e) {
+                TA p[M], w;
+                neighbour_data<D, P, UNIT, TA>(gp, S.t, a.spts + (size_t)S.at(e) * D, inv_h,
+                                               inv_r2, a.weight, p, w);
+#pragma unroll
+                for (int u = 0; u < M; ++u) {
+                    TA wp = w * p[u];
+#pragma unroll
+                    for (int v = u; v < M; ++v)
+                        G[tri<M>(u, v)] = __builtin_fma(wp, p[v], G[tri<M>(u, v)]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < MM; ++j) R[j] = (double)G[j];
+        }
+#pragma unroll
+        for (int u = 0; u < M; ++u) R[tri<M>(u, u)] += a.lambda;
+        bool ok = cholesky<M>(R, idg);
+#pragma unroll
+        for (int u = 0; u < M; ++u) y[u] = u == 0 ? 1.0 : 0.0;
+        chol_solve<M>(R, idg, y);
+        if (ok && MIXED && a.refine) {
+            // Iterative refinement: y += G32^{-1} (e_0 - (G + lambda I) y), the
+            // residual formed in FP64 from the same FP32 per-neighbour data.
+            // One step normally suffices; ill-conditioned targets take up to
+            // kMaxRefine, and a correction that does not shrink marks the
+            // target singular at FP32 assembly accuracy.
+            for (int step = 0; step < kMaxRefine; ++step) {
+                double res[M];
+#pragma unroll
+                for (int u = 0; u < M; ++u) res[u] = (u == 0 ? 1.0 : 0.0) - a.lambda * y[u];
+                for (int e = 0; e < n; ++e) {
+                    TA p[M], w;
+                    neighbour_data<D, P, UNIT, TA>(gp, S.t, a.spts + (size_t)S.at(e) * D, inv_h,
+                                                   inv_r2, a.weight, p, w);
+                    double py = 0.0;
+#pragma unroll
+                    for (int u = 0; u < M; ++u) py = __builtin_fma((double)p[u], y[u], py);
+                    double c = -(double)w * py;
+#pragma unroll
+                    for (int u = 0; u < M; ++u) res[u] = __builtin_fma(c, (double)p[u], res[u]);
+                }
+                chol_solve<M>(R, idg, res);
+                double ny = 0.0, nd = 0.0;
+#pragma unroll
+                for (int u = 0; u < M; ++u) {
+                    ny = fmax(ny, fabs(y[u]));
+                    nd = fmax(nd, fabs(res[u]));
+                    y[u] += res[u];
+                }
+                if (nd <= 1e-8 * ny) break;
+                if (!(nd <= 0.5 * ny) || step == kMaxRefine - 1) {
+                    if (!(nd <= 1e-5 * ny)) ok = false;
+                    break;
+                }
+            }
+        }
+        if (!ok) st |= PCMS_TGT_SINGULAR;
+    }
+    if ((st & 0xF) == PCMS_TGT_OK) {
+        const double inv_h = 1.0 / sqrt(r2);
+        const double inv_r2 = 1.0 / r2;
+        const double *sv0 = a.svals + (size_t)S.at(0) * a.nf;
+        for (int l0 = 0; l0 < a.nf; l0 += kFieldChunk) {
+            double acc[kFieldChunk], fref[kFieldChunk];
+#pragma unroll
+            for (int l = 0; l < kFieldChunk; ++l) {
+                acc[l] = 0.0;
+                // centring leaves the fit unchanged only without regularisation
+                fref[l] = (MIXED && a.lambda == 0.0 && l0 + l < a.nf) ? sv0[l0 + l] : 0.0;
+            }
+            for (int e = 0; e < n; ++e) {
+                const int pe = S.at(e);
+                TA p[M], w;
+                neighbour_data<D, P, UNIT, TA>(gp, S.t, a.spts + (size_t)pe * D, inv_h, inv_r2,
+                                               a.weight, p, w);
+                double py = 0.0;
+#pragma unroll
+                for (int u = 0; u < M; ++u) py = __builtin_fma((double)p[u], y[u], py);
+                const double N = (double)w * py;
+                const double *sv = a.svals + (size_t)pe * a.nf + l0;
+#pragma unroll
+                for (int l = 0; l < kFieldChunk; ++l)
+                    if (l0 + l < a.nf) acc[l] = __builtin_fma(N, sv[l] - fref[l], acc[l]);
+            }
+#pragma unroll
+            for (int l = 0; l < kFieldChunk; ++l)
+                if (l0 + l < a.nf) a.out[(size_t)(l0 + l) * a.n_tgt + ti] = acc[l] + fref[l];
+        }
+    } else {
+        for (int l = 0; l < a.nf; ++l) a.out[(size_t)l * a.n_tgt + ti] = NAN;
+    }
+    if (a.status) a.status[ti] = (uint8_t)st;
+    return st;
+}
+
+}  // namespace pcms

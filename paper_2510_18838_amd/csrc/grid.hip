@@ -1,0 +1,386 @@
+// Uniform-grid spatial hash (PCMS paper, Section 3.3: a single-level uniform
+// grid as the point-localisation structure), built on the GPU:
+//   bounding box -> bucket sizing -> bucket id per point -> stable LSD radix
+//   sort of the bucket ids (8-bit digits, LDS histograms and LDS wave
+//   multisplit ranking) -> per-bucket start offsets -> sorted coordinates.
+// The sort is stable, so within a bucket sources keep ascending index order
+// and the whole layout is deterministic.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+namespace pcms {
+
+namespace {
+
+constexpr int kSortThreads = 256;          // 4 waves of 64
+constexpr int kSortRounds = 16;            // items per thread per block
+constexpr int kSortItems = kSortThreads * kSortRounds;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4 * kScanThreads;
+
+__device__ inline long long ordered_key(double x)
+{
+    long long b = __double_as_longlong(x);
+    return b >= 0 ? b : (b ^ 0x7fffffffffffffffLL);
+}
+
+__device__ inline double ordered_val(long long k)
+{
+    long long b = k >= 0 ? k : (k ^ 0x7fffffffffffffffLL);
+    return __longlong_as_double(b);
+}
+
+__global__ void k_bbox_init(long long *bb, int dim)
+{
+    int k = threadIdx.x;
+    if (k < dim) {
+        bb[k] = 0x7fffffffffffffffLL;              // running min
+        bb[dim + k] = (long long)0x8000000000000000ULL;  // running max
+    }
+}
+
+// Per-dimension min/max of the points; one atomic per wave per dimension.
+__global__ void k_bbox(const double *__restrict__ pts, int64_t n, int dim, long long *bb)
+{
+    for (int k = 0; k < dim; ++k) {
+        double mn = INFINITY, mx = -INFINITY;
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            double x = pts[i * dim + k];
+            mn = fmin(mn, x);
+            mx = fmax(mx, x);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            mn = fmin(mn, __shfl_xor(mn, off));
+            mx = fmax(mx, __shfl_xor(mx, off));
+        }
+        if ((threadIdx.x & 63) == 0 && mn <= mx) {
+            atomicMin(&bb[k], ordered_key(mn));
+            atomicMax(&bb[dim + k], ordered_key(mx));
+        }
+    }
+}
+
+// Chooses the bucket widths (one thread).
+__global__ void k_grid_params(const long long *bb, int dim, int64_t n, const double *g,
+                              double cell_width, double pts_per_cell, int cap, GridParams *gp)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double lo[kMaxDim], hi[kMaxDim];
+    for (int k = 0; k < dim; ++k) {
+        lo[k] = ordered_val(bb[k]);
+        hi[k] = ordered_val(bb[dim + k]);
+    }
+    grid_params_compute(lo, hi, dim, n, g, cell_width, pts_per_cell, cap, gp);
+}
+
+__global__ void k_bucket_keys(const GridParams *__restrict__ gp, const double *__restrict__ pts,
+                              int64_t n, unsigned *__restrict__ keys, int *__restrict__ vals)
+{
+    const GridParams p = *gp;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        keys[i] = bucket_key(p, pts + i * p.dim);
+        vals[i] = (int)i;
+    }
+}
+
+// --- stable LSD radix sort, 8-bit digits --------------------------------------
+
+__global__ void __launch_bounds__(kSortThreads)
+k_digit_hist(const unsigned *__restrict__ keys, int n, int shift, int *__restrict__ hist, int nb)
+{
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int base = blockIdx.x * kSortItems;
+    for (int r = 0; r < kSortRounds; ++r) {
+        int i = base + r * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];   // digit-major
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_digit_scatter(const unsigned *__restrict__ kin, const int *__restrict__ vin, int n, int shift,
+                const int *__restrict__ offs, int nb, unsigned *__restrict__ kout,
+                int *__restrict__ vout)
+{
+    __shared__ int running[256];
+    __shared__ int wave_cnt[4][256];
+    const int t = threadIdx.x;
+    const int w = t >> 6;
+    const int lane = t & 63;
+    running[t] = offs[t * nb + blockIdx.x];
+    int base = blockIdx.x * kSortItems;
+    for (int r = 0; r < kSortRounds; ++r) {
+        if (base + r * kSortThreads >= n) break;      // uniform across the block
+        int i = base + r * kSortThreads + t;
+        bool valid = i < n;
+        unsigned key = valid ? kin[i] : 0u;
+        int val = valid ? vin[i] : 0;
+        int digit = (key >> shift) & 255;
+        unsigned long long bits[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) bits[b] = __ballot((digit >> b) & 1);
+        const unsigned long long mask = digit_match(__ballot(valid), bits, digit);
+        wave_cnt[0][t] = 0;
+        wave_cnt[1][t] = 0;
+        wave_cnt[2][t] = 0;
+        wave_cnt[3][t] = 0;
+        __syncthreads();
+        if (valid && (mask & lanes_below(lane)) == 0) wave_cnt[w][digit] = __popcll(mask);
+        __syncthreads();
+        if (valid) {
+            int pos = scatter_slot(running[digit], wave_cnt, w, digit, mask, lane);
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        running[t] += wave_cnt[0][t] + wave_cnt[1][t] + wave_cnt[2][t] + wave_cnt[3][t];
+        __syncthreads();
+    }
+}
+
+// --- exclusive scan of int32 (3 phases, recursive on the block sums) ----------
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_blocks(int *__restrict__ data, int n, int *__restrict__ sums)
+{
+    __shared__ int s[kScanThreads];
+    int base = blockIdx.x * kScanItems + threadIdx.x * 4;
+    int v[4];
+    int local = 0;
+    for (int j = 0; j < 4; ++j) {
+        v[j] = (base + j < n) ? data[base + j] : 0;
+        local += v[j];
+    }
+    s[threadIdx.x] = local;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        int x = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += x;
+        __syncthreads();
+    }
+    int run = s[threadIdx.x] - local;   // exclusive prefix of this thread
+    for (int j = 0; j < 4; ++j) {
+        if (base + j < n) data[base + j] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == kScanThreads - 1) sums[blockIdx.x] = s[threadIdx.x];
+}
+
+__global__ void k_scan_add(int *__restrict__ data, int n, const int *__restrict__ sums)
+{
+    int i = blockIdx.x * kScanItems + threadIdx.x;
+    int add = sums[blockIdx.x];
+    for (int j = 0; j < 4; ++j, i += kScanThreads)
+        if (i < n) data[i] += add;
+}
+
+pcms_status scan_exclusive(int *data, int n, int *scratch, hipStream_t s)
+{
+    int nb = (n + kScanItems - 1) / kScanItems;
+    if (nb <= 0) return PCMS_OK;
+    k_scan_blocks<<<nb, kScanThreads, 0, s>>>(data, n, scratch);
+    PCMS_HIP(hipGetLastError());
+    if (nb > 1) {
+        pcms_status st = scan_exclusive(scratch, nb, scratch + nb, s);
+        if (st != PCMS_OK) return st;
+        k_scan_add<<<nb, kScanThreads, 0, s>>>(data, n, scratch);
+        PCMS_HIP(hipGetLastError());
+    }
+    return PCMS_OK;
+}
+
+int scan_scratch_ints(int n)
+{
+    int total = 0;
+    while (n > 1) {
+        n = (n + kScanItems - 1) / kScanItems;
+        total += n;
+    }
+    return total + 1;
+}
+
+int key_bits(int n_cells_cap)
+{
+    int b = 0;
+    while (b < 31 && (1u << b) < (unsigned)n_cells_cap) ++b;
+    return b;
+}
+
+// Sorts (keys, vals) stably by key; the result ends up in (k0, v0).
+pcms_status radix_sort(unsigned *k0, int *v0, unsigned *k1, int *v1, int n, int bits, int *hist,
+                       int *scan_scratch, hipStream_t s)
+{
+    int nb = (n + kSortItems - 1) / kSortItems;
+    if (nb == 0) return PCMS_OK;
+    int passes = std::max(1, (bits + 7) / 8);
+    unsigned *kin = k0, *kout = k1;
+    int *vin = v0, *vout = v1;
+    for (int ps = 0; ps < passes; ++ps) {
+        int shift = 8 * ps;
+        k_digit_hist<<<nb, kSortThreads, 0, s>>>(kin, n, shift, hist, nb);
+        PCMS_HIP(hipGetLastError());
+        pcms_status st = scan_exclusive(hist, 256 * nb, scan_scratch, s);
+        if (st != PCMS_OK) return st;
+        k_digit_scatter<<<nb, kSortThreads, 0, s>>>(kin, vin, n, shift, hist, nb, kout, vout);
+        PCMS_HIP(hipGetLastError());
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    if (kin != k0) {
+        PCMS_HIP(hipMemcpyAsync(k0, kin, sizeof(unsigned) * (size_t)n, hipMemcpyDeviceToDevice, s));
+        PCMS_HIP(hipMemcpyAsync(v0, vin, sizeof(int) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    }
+    return PCMS_OK;
+}
+
+size_t sort_scratch_bytes(int n)
+{
+    int nb = (n + kSortItems - 1) / kSortItems;
+    size_t ints = (size_t)256 * nb + (size_t)scan_scratch_ints(256 * nb);
+    return sizeof(unsigned) * 2 * (size_t)n + sizeof(int) * 2 * (size_t)n + sizeof(int) * ints + 256;
+}
+
+// cell_start[c] = first sorted position whose key is >= c, for c in [0, n_cells].
+__global__ void k_cell_start(const GridParams *__restrict__ gp, const unsigned *__restrict__ keys,
+                             int n, int *__restrict__ cell_start)
+{
+    int n_cells = gp->n_cells;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c <= n_cells; c += gridDim.x * blockDim.x) {
+        int lo = 0, hi = n;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (keys[mid] < (unsigned)c) lo = mid + 1;
+            else hi = mid;
+        }
+        cell_start[c] = lo;
+    }
+}
+
+__global__ void k_gather_pts(const double *__restrict__ src, const int *__restrict__ perm,
+                             int64_t n, int dim, double *__restrict__ spts)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        int64_t j = perm[p];
+        for (int k = 0; k < dim; ++k) spts[p * dim + k] = src[j * dim + k];
+    }
+}
+
+__global__ void k_gather_vals(const double *__restrict__ vals, const int *__restrict__ perm,
+                              int64_t n, int nf, double *__restrict__ svals)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        int64_t j = perm[p];
+        for (int l = 0; l < nf; ++l) svals[p * nf + l] = vals[(int64_t)l * n + j];
+    }
+}
+
+int grid_blocks(int64_t n, int tpb)
+{
+    int64_t b = (n + tpb - 1) / tpb;
+    return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 65536);
+}
+
+}  // namespace
+
+int cells_cap_for(int64_t n_src)
+{
+    int64_t c = 2 * n_src + 64;
+    return (int)std::min<int64_t>(c, (int64_t)1 << 30);
+}
+
+pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
+                              double pts_per_cell, hipStream_t s)
+{
+    const int dim = grid->dim;
+    const int n = (int)grid->n_src;
+    // scratch: bbox keys + metric copy + sort buffers
+    size_t bytes = 256 + sort_scratch_bytes(n) + 64 * sizeof(double);
+    void *raw = nullptr;
+    pcms_status st = scratch_alloc(&raw, bytes, s);
+    if (st != PCMS_OK) return st;
+    char *cur = (char *)raw;
+    long long *bb = (long long *)cur;
+    cur += 128;
+    double *gdev = (double *)cur;
+    cur += 128;
+    unsigned *k0 = (unsigned *)cur;
+    cur += sizeof(unsigned) * (size_t)n;
+    unsigned *k1 = (unsigned *)cur;
+    cur += sizeof(unsigned) * (size_t)n;
+    int *v1 = (int *)cur;
+    cur += sizeof(int) * (size_t)n;
+    int nb = (n + kSortItems - 1) / kSortItems;
+    int *hist = (int *)cur;
+    cur += sizeof(int) * (size_t)256 * nb;
+    int *scan_scratch = (int *)cur;
+
+    PCMS_HIP(hipMemcpyAsync(gdev, grid->g, sizeof(double) * dim, hipMemcpyHostToDevice, s));
+    k_bbox_init<<<1, 64, 0, s>>>(bb, dim);
+    PCMS_HIP(hipGetLastError());
+    k_bbox<<<grid_blocks(n, 256), 256, 0, s>>>(src, n, dim, bb);
+    PCMS_HIP(hipGetLastError());
+    k_grid_params<<<1, 1, 0, s>>>(bb, dim, n, gdev, cell_width, pts_per_cell, grid->n_cells_cap,
+                                  grid->params);
+    PCMS_HIP(hipGetLastError());
+    k_bucket_keys<<<grid_blocks(n, 256), 256, 0, s>>>(grid->params, src, n, k0, grid->perm);
+    PCMS_HIP(hipGetLastError());
+    st = radix_sort(k0, grid->perm, k1, v1, n, key_bits(grid->n_cells_cap), hist, scan_scratch, s);
+    if (st != PCMS_OK) return st;
+    k_cell_start<<<grid_blocks((int64_t)grid->n_cells_cap + 1, 256), 256, 0, s>>>(
+        grid->params, k0, n, grid->cell_start);
+    PCMS_HIP(hipGetLastError());
+    k_gather_pts<<<grid_blocks(n, 256), 256, 0, s>>>(src, grid->perm, n, dim, grid->spts);
+    PCMS_HIP(hipGetLastError());
+    scratch_free(raw, s);
+    return PCMS_OK;
+}
+
+pcms_status sort_targets(const Grid *grid, const double *tgt, int64_t n_tgt, int *tperm,
+                         hipStream_t s)
+{
+    const int n = (int)n_tgt;
+    size_t bytes = sort_scratch_bytes(n);
+    void *raw = nullptr;
+    pcms_status st = scratch_alloc(&raw, bytes, s);
+    if (st != PCMS_OK) return st;
+    char *cur = (char *)raw;
+    unsigned *k0 = (unsigned *)cur;
+    cur += sizeof(unsigned) * (size_t)n;
+    unsigned *k1 = (unsigned *)cur;
+    cur += sizeof(unsigned) * (size_t)n;
+    int *v1 = (int *)cur;
+    cur += sizeof(int) * (size_t)n;
+    int nb = (n + kSortItems - 1) / kSortItems;
+    int *hist = (int *)cur;
+    cur += sizeof(int) * (size_t)256 * nb;
+    int *scan_scratch = (int *)cur;
+    k_bucket_keys<<<grid_blocks(n, 256), 256, 0, s>>>(grid->params, tgt, n, k0, tperm);
+    PCMS_HIP(hipGetLastError());
+    st = radix_sort(k0, tperm, k1, v1, n, key_bits(grid->n_cells_cap), hist, scan_scratch, s);
+    if (st != PCMS_OK) return st;
+    scratch_free(raw, s);
+    return PCMS_OK;
+}
+
+pcms_status gather_values(const Grid *grid, const double *vals, int n_fields, double *svals,
+                          hipStream_t s)
+{
+    k_gather_vals<<<grid_blocks(grid->n_src, 256), 256, 0, s>>>(vals, grid->perm, grid->n_src,
+                                                               n_fields, svals);
+    PCMS_HIP(hipGetLastError());
+    return PCMS_OK;
+}
+
+}  // namespace pcms

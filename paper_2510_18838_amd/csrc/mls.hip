@@ -1,0 +1,215 @@
+// Neighbour-list and field-transfer kernels: one lane per target, targets in
+// bucket order so that the lanes of a wave search overlapping stencils.  The
+// per-target work (search, moment assembly, Cholesky, evaluation) is in
+// fit.h / search.h; this file holds the kernels and their launchers.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "fit.h"
+#include "internal.h"
+
+namespace pcms {
+
+namespace {
+
+// Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// range of (spatially sorted) target blocks so its L2 sees neighbouring work.
+__device__ __forceinline__ int logical_block(int n_blocks)
+{
+    const int per = (n_blocks + 7) >> 3;
+    return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+}
+
+__device__ __forceinline__ void add_summary(int32_t *summary, int st, bool active)
+{
+    if (!summary) return;
+    unsigned long long b1 = __ballot(active && (st & 0xF) == PCMS_TGT_UNDERDETERMINED);
+    unsigned long long b2 = __ballot(active && (st & 0xF) == PCMS_TGT_SINGULAR);
+    unsigned long long b3 = __ballot(active && (st & 0xF) == PCMS_TGT_RADIUS_EXHAUSTED);
+    unsigned long long b4 = __ballot(active && (st & PCMS_TGT_CAPPED));
+    if ((threadIdx.x & 63) == 0) {
+        if (b1) atomicAdd(&summary[0], (int)__popcll(b1));
+        if (b2) atomicAdd(&summary[1], (int)__popcll(b2));
+        if (b3) atomicAdd(&summary[2], (int)__popcll(b3));
+        if (b4) atomicAdd(&summary[3], (int)__popcll(b4));
+    }
+}
+
+template <int D, bool UNIT>
+__global__ void __launch_bounds__(256) k_neighbors(KArgs a)
+{
+    extern __shared__ int lds[];
+    const int lb = logical_block(a.n_blocks);
+    if (lb >= a.n_blocks) return;
+    const int i = lb * blockDim.x + threadIdx.x;
+    const bool active = i < a.n_tgt;
+    int st = 0;
+    if (active) {
+        const GridParams gp = *a.gp;
+        st = nbr_target<D, UNIT>(a, gp, i, lds, (int)threadIdx.x, (int)blockDim.x);
+    }
+    add_summary(a.summary, st, active);
+}
+
+template <int D, int P, bool MIXED, bool UNIT>
+__global__ void __launch_bounds__(256) k_transfer(KArgs a)
+{
+    extern __shared__ int lds[];
+    const int lb = logical_block(a.n_blocks);
+    if (lb >= a.n_blocks) return;
+    const int i = lb * blockDim.x + threadIdx.x;
+    const bool active = i < a.n_tgt;
+    int st = 0;
+    if (active) {
+        const GridParams gp = *a.gp;
+        st = xfer_target<D, P, MIXED, UNIT>(a, gp, i, lds, (int)threadIdx.x, (int)blockDim.x);
+    }
+    add_summary(a.summary, st, active);
+}
+
+__global__ void k_zero_ints(int32_t *p, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+using KernelFn = void (*)(KArgs);
+
+template <int D, bool UNIT>
+KernelFn pick_nbr()
+{
+    return k_neighbors<D, UNIT>;
+}
+
+template <int D, int P, bool UNIT>
+KernelFn pick_xfer(bool mixed)
+{
+    return mixed ? (KernelFn)k_transfer<D, P, true, UNIT> : (KernelFn)k_transfer<D, P, false, UNIT>;
+}
+
+template <bool UNIT>
+KernelFn xfer_table(int d, int p, bool mixed)
+{
+#define PCMS_CASE(DD)                                               \
+    case DD:                                                        \
+        return p == 0 ? pick_xfer<DD, 0, UNIT>(mixed)               \
+             : p == 1 ? pick_xfer<DD, 1, UNIT>(mixed)               \
+                      : pick_xfer<DD, 2, UNIT>(mixed);
+    switch (d) {
+        PCMS_CASE(1)
+        PCMS_CASE(2)
+        PCMS_CASE(3)
+        PCMS_CASE(4)
+        PCMS_CASE(5)
+    }
+#undef PCMS_CASE
+    return nullptr;
+}
+
+template <bool UNIT>
+KernelFn nbr_table(int d)
+{
+    switch (d) {
+    case 1: return pick_nbr<1, UNIT>();
+    case 2: return pick_nbr<2, UNIT>();
+    case 3: return pick_nbr<3, UNIT>();
+    case 4: return pick_nbr<4, UNIT>();
+    case 5: return pick_nbr<5, UNIT>();
+    }
+    return nullptr;
+}
+
+bool unit_metric(const Grid *g)
+{
+    for (int k = 0; k < g->dim; ++k)
+        if (g->g[k] != 1.0) return false;
+    return true;
+}
+
+// Per-lane LDS words: the kept list (k_cap entries), which also serves as a
+// buffer of k_cap / 2 doubles during the radius search (at least one).
+int lane_words(int k_cap) { return k_cap < 2 ? 2 : k_cap; }
+
+int pick_block(int requested, int k_cap)
+{
+    int b = requested > 0 ? requested : 64;
+    // the per-lane lists must fit 64 KiB of LDS per workgroup
+    while (b > 64 && (size_t)b * lane_words(k_cap) * sizeof(int) > 65536) b >>= 1;
+    return b;
+}
+
+KArgs base_args(const LaunchSpec &ls, int block)
+{
+    KArgs a{};
+    a.gp = ls.grid->params;
+    a.cs = ls.grid->cell_start;
+    a.spts = ls.grid->spts;
+    a.perm = ls.grid->perm;
+    a.tgt = ls.tgt;
+    a.tperm = ls.tperm;
+    a.n_tgt = (int)ls.n_tgt;
+    a.mode = ls.radius.mode;
+    a.k = ls.radius.k;
+    a.n_min = ls.radius.n_min;
+    a.max_iter = ls.radius.max_iter;
+    a.r = ls.radius.r;
+    a.k_cap = ls.k_cap;
+    a.n_blocks = (int)((ls.n_tgt + block - 1) / block);
+    a.words = lane_words(ls.k_cap);
+    a.summary = ls.summary;
+    return a;
+}
+
+}  // namespace
+
+pcms_status zero_ints(int32_t *p, int n, hipStream_t s)
+{
+    k_zero_ints<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+    PCMS_HIP(hipGetLastError());
+    return PCMS_OK;
+}
+
+pcms_status launch_neighbors(const LaunchSpec &ls, int32_t *nbr, int32_t *n_kept,
+                             int32_t *n_found, double *r2, uint8_t *status, hipStream_t s)
+{
+    if (ls.n_tgt == 0) return PCMS_OK;
+    const int block = pick_block(ls.block, ls.k_cap);
+    KArgs a = base_args(ls, block);
+    a.nbr = nbr;
+    a.n_kept = n_kept;
+    a.n_found = n_found;
+    a.r2 = r2;
+    a.status = status;
+    KernelFn fn = unit_metric(ls.grid) ? nbr_table<true>(ls.grid->dim) : nbr_table<false>(ls.grid->dim);
+    const int launch = ((a.n_blocks + 7) / 8) * 8;
+    const size_t shm = (size_t)block * lane_words(ls.k_cap) * sizeof(int);
+    hipLaunchKernelGGL(fn, dim3(launch), dim3(block), shm, s, a);
+    PCMS_HIP(hipGetLastError());
+    return PCMS_OK;
+}
+
+pcms_status launch_transfer(const LaunchSpec &ls, const double *svals, int n_fields, int degree,
+                            int weight, int precision, double lambda, double *out,
+                            uint8_t *status, hipStream_t s)
+{
+    if (ls.n_tgt == 0) return PCMS_OK;
+    const int block = pick_block(ls.block, ls.k_cap);
+    KArgs a = base_args(ls, block);
+    a.svals = svals;
+    a.nf = n_fields;
+    a.weight = weight;
+    a.refine = precision == PCMS_MIXED_REFINE;
+    a.lambda = lambda;
+    a.out = out;
+    a.status = status;
+    const bool mixed = precision != PCMS_FP64;
+    KernelFn fn = unit_metric(ls.grid) ? xfer_table<true>(ls.grid->dim, degree, mixed)
+                                       : xfer_table<false>(ls.grid->dim, degree, mixed);
+    const int launch = ((a.n_blocks + 7) / 8) * 8;
+    const size_t shm = (size_t)block * lane_words(ls.k_cap) * sizeof(int);
+    hipLaunchKernelGGL(fn, dim3(launch), dim3(block), shm, s, a);
+    PCMS_HIP(hipGetLastError());
+    return PCMS_OK;
+}
+
+}  // namespace pcms

@@ -1,0 +1,349 @@
+// Per-target neighbour search on the uniform grid, one lane per target.
+//
+// Selection follows the PCMS paper, Section 3.2.1: the source set of target
+// t is { s_j : phi(s_j, t) > 0 }, i.e. the sources strictly inside the
+// support radius.  The distance is the metric
+//     D = fma(u_{d-1}, u_{d-1}, ... fma(u_1, u_1, u_0 * u_0)),
+//     u_k = (t_k - s_k) * g_k,
+// evaluated in FP64 in this exact order, so the predicate D < r^2 is bit
+// reproducible.  The radius is fixed, grown by doubling r^2 until a minimum
+// count is met (Section 3.2.1), or set to the k-th smallest D.  Above k_cap
+// sources the k_cap smallest by (D, source index) are kept.
+//
+// Stencil walk: buckets are row-major with dimension 0 fastest, so for every
+// row (c_1..c_{d-1}) the buckets c_0 in [a, b] form one contiguous range of
+// sorted sources.  Rows whose slab is farther than the radius are skipped and
+// each row's c_0 range is narrowed to the chord of the ball in that slab.
+#pragma once
+
+#include "device_common.h"
+
+namespace pcms {
+
+template <int D, bool UNIT>
+PCMS_HD PCMS_INLINE double metric_d2(const double (&t)[D], const double *__restrict__ s,
+                                            const GridParams &p)
+{
+    double u = UNIT ? (t[0] - s[0]) : (t[0] - s[0]) * p.g[0];
+    double acc = u * u;
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+        u = UNIT ? (t[k] - s[k]) : (t[k] - s[k]) * p.g[k];
+        acc = __builtin_fma(u, u, acc);
+    }
+    return acc;
+}
+
+// Calls f(p, D) for every sorted source p in the buckets that can hold a
+// source with D < rho2 (a superset of the ball).  rho2 may be +inf.
+template <int D, bool UNIT, class F>
+PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs,
+                                     const double *__restrict__ spts, const double (&t)[D],
+                                     double rho2, F &&f)
+{
+    const double rho = sqrt(rho2);
+    int a[D], b[D], c[D];
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+        double half = rho / gp.g[k] * (1.0 + 1e-9) + fabs(t[k]) * 1e-15 + 1e-300;
+        a[k] = bucket_of(gp, k, t[k] - half);
+        b[k] = bucket_of(gp, k, t[k] + half);
+        c[k] = a[k];
+    }
+    for (;;) {
+        // squared metric distance from t to this row's slab (boxes widened
+        // slightly so rounding in the bucket assignment cannot hide a source)
+        double m2 = 0.0;
+        int row = 0;
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            double blo = gp.lo[k] + (double)c[k] * gp.w[k];
+            double bhi = blo + gp.w[k];
+            double pad = 1e-7 * gp.w[k];
+            // the first and last buckets also hold clamped coordinates
+            if (c[k] == 0) blo = -INFINITY;
+            if (c[k] == gp.n[k] - 1) bhi = INFINITY;
+            double dlt = fmax(fmax(blo - pad - t[k], t[k] - bhi - pad), 0.0) * gp.g[k];
+            m2 = __builtin_fma(dlt, dlt, m2);
+            row += c[k] * gp.stride[k];
+        }
+        if (m2 <= rho2 * (1.0 + 1e-9)) {
+            double rem2 = fmax(rho2 - m2 * (1.0 - 1e-9), 0.0);
+            double half0 = sqrt(rem2) / gp.g[0] * (1.0 + 1e-9) + fabs(t[0]) * 1e-15 + 1e-300;
+            int a0 = bucket_of(gp, 0, t[0] - half0);
+            int b0 = bucket_of(gp, 0, t[0] + half0);
+            int beg = cs[row + a0];
+            int end = cs[row + b0 + 1];
+            for (int p = beg; p < end; ++p) {
+                const double *s = spts + (size_t)p * D;
+                f(p, metric_d2<D, UNIT>(t, s, gp));
+            }
+        }
+        int k = 1;
+        while (k < D) {
+            if (c[k] < b[k]) {
+                c[k]++;
+                break;
+            }
+            c[k] = a[k];
+            k++;
+        }
+        if (k >= D) break;
+    }
+}
+
+// Per-lane search state.  The lane's `words` LDS words are interleaved by
+// lane: word e of this lane is base[e * ls + lane].  They hold the kept list
+// (k_cap entries) and, during the radius search, a buffer of words / 2
+// doubles, double j split over this lane's words 2j (low half) and 2j + 1.
+template <int D, bool UNIT>
+struct LaneSearch {
+    const GridParams &gp;
+    const int *__restrict__ cs;
+    const double *__restrict__ spts;
+    const int *__restrict__ perm;
+    double t[D];
+    int *base;  // block LDS base
+    int lane;   // lane index inside the block
+    int ls;     // lanes per block
+    int k_cap;
+    int words;  // LDS words per lane (>= max(k_cap, 2))
+
+    PCMS_HD PCMS_INLINE int &at(int e)
+    {
+#ifdef PCMS_HOST_EMULATION
+        if (e < 0 || e >= words) pcms_emu_lds_fault(e, words);
+#endif
+        return base[e * ls + lane];
+    }
+    PCMS_HD PCMS_INLINE void dstore(int j, double v)
+    {
+        unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        at(2 * j) = (int)(unsigned)(b & 0xffffffffull);
+        at(2 * j + 1) = (int)(unsigned)(b >> 32);
+    }
+    PCMS_HD PCMS_INLINE double dload(int j)
+    {
+        unsigned long long lo = (unsigned)at(2 * j);
+        unsigned long long hi = (unsigned)at(2 * j + 1);
+        return __builtin_bit_cast(double, (hi << 32) | lo);
+    }
+
+    template <class F>
+    PCMS_HD PCMS_INLINE void each(double rho2, F &&f)
+    {
+        walk<D, UNIT>(gp, cs, spts, t, rho2, f);
+    }
+
+    // Squared metric distance from t to the farthest corner of the bucket
+    // box; every source lies closer, so a larger radius covers all sources.
+    PCMS_HD double far2() const
+    {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            double lo = gp.lo[k], hi = gp.lo[k] + gp.n[k] * gp.w[k];
+            double dd = fmax(fabs(t[k] - lo), fabs(hi - t[k])) * gp.g[k];
+            acc += dd * dd;
+        }
+        return acc * (1.0 + 1e-6) + 1e-300;
+    }
+
+    // Collects every source with D < r2 into the list (up to k_cap); returns the count.
+    PCMS_HD int collect(double r2)
+    {
+        int n = 0;
+        each(r2, [&](int p, double d2) {
+            if (d2 < r2) {
+                if (n < k_cap) at(n) = p;
+                ++n;
+            }
+        });
+        return n;
+    }
+
+    // Radius of a ball expected to hold k sources, from the bucket counts
+    // around t (no point loads).
+    PCMS_HD double knn_radius_guess(int k) const
+    {
+        int a[D], b[D], c[D];
+        double vol = 1.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            int cj = bucket_of(gp, j, t[j]);
+            a[j] = max(cj - 1, 0);
+            b[j] = min(cj + 1, gp.n[j] - 1);
+            c[j] = a[j];
+            vol *= (double)(b[j] - a[j] + 1) * gp.w[j] * gp.g[j];
+        }
+        long long count = 0;
+        for (;;) {
+            int row = 0;
+#pragma unroll
+            for (int j = 1; j < D; ++j) row += c[j] * gp.stride[j];
+            count += cs[row + b[0] + 1] - cs[row + a[0]];
+            int j = 1;
+            while (j < D) {
+                if (c[j] < b[j]) {
+                    c[j]++;
+                    break;
+                }
+                c[j] = a[j];
+                j++;
+            }
+            if (j >= D) break;
+        }
+        // unit-ball volume pi^(D/2) / Gamma(D/2 + 1)
+        const double vball = D == 1 ? 2.0 : D == 2 ? M_PI : D == 3 ? 4.18879020478639098
+                           : D == 4 ? 4.93480220054467931 : 5.26378901489003940;
+        if (count <= 0) {
+            double half = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) half = fmax(half, 1.5 * gp.w[j] * gp.g[j]);
+            return 2.0 * half;
+        }
+        return pow((double)k * vol / ((double)count * vball), 1.0 / D);
+    }
+
+    // Exact k-th smallest D (1-based) over all sources, given a bracket:
+    // #(D < lo) = c_lo < k, and hi a first guess for an upper bound (grown
+    // when #(D < hi) < k).  Each round counts the sources of [lo, hi) into 8
+    // sub-intervals with one walk; once the interval holding the k-th has at
+    // most `sb` (<= words / 2) sources they are copied into the lane's LDS
+    // buffer and ranked.
+    PCMS_HD double kth(int k, double lo, int c_lo, double hi, int sb)
+    {
+        constexpr int NB = 8;
+        const double farr = far2();
+        for (int it = 0; it < 400; ++it) {
+            double sp[NB];
+            const bool from_zero = (lo == 0.0);
+#pragma unroll
+            for (int j = 0; j < NB - 1; ++j) {
+                // from zero: equal expected counts, (j+1)/NB of the volume;
+                // otherwise linear in D
+                double f = from_zero ? pow((double)(j + 1) / NB, 2.0 / D) : (double)(j + 1) / NB;
+                double sj = lo + (hi - lo) * f;
+                sp[j] = fmin(fmax(sj, lo), hi);
+            }
+            sp[NB - 1] = hi;
+            int cnt[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) cnt[j] = 0;
+            const double l0 = lo, h0 = hi;
+            double vmin = h0;   // smallest D in [lo, hi) and its multiplicity
+            int neq = 0;
+            each(h0, [&](int, double d2) {
+                if (d2 >= l0 && d2 < h0) {
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) cnt[j] += d2 < sp[j];
+                    if (d2 < vmin) {
+                        vmin = d2;
+                        neq = 0;
+                    }
+                    neq += d2 == vmin;
+                }
+            });
+            if (c_lo + cnt[NB - 1] < k) {     // the k-th lies at or above hi
+                // every source has D < farr, so the count reaches k there
+                // (k <= n_src); nothing above it is left to search
+                if (!(hi < farr)) return hi;
+                c_lo += cnt[NB - 1];
+                lo = hi;
+                hi = fmin(fmax(hi * 16.0, farr * 1e-12), farr);
+                continue;
+            }
+            // #(D < vmin) = c_lo: the k-th is vmin when its copies reach rank k
+            if (c_lo + neq >= k) return vmin;
+            int bsel = NB - 1;
+#pragma unroll
+            for (int j = NB - 1; j >= 0; --j)
+                if (c_lo + cnt[j] >= k) bsel = j;
+            int below = 0;
+            double nlo = lo, nhi = hi;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                if (j + 1 == bsel) {
+                    below = cnt[j];
+                    nlo = sp[j];
+                }
+                if (j == bsel) nhi = sp[j];
+            }
+            int nin = cnt[bsel] - below;
+            lo = nlo;
+            hi = nhi;
+            c_lo += below;
+            if (nin == cnt[NB - 1] && vmin >= lo) {
+                // no split separated the values (many equal ones): step past
+                // the smallest, whose copies all rank below k
+                lo = nextafter(vmin, INFINITY);
+                c_lo += neq;
+                nin -= neq;
+            }
+            if (nin <= sb) {
+                int n = 0;
+                const double l1 = lo, h1 = hi;
+                each(h1, [&](int, double d2) {
+                    if (d2 >= l1 && d2 < h1 && n < sb) dstore(n++, d2);
+                });
+                const int r = k - c_lo;   // 1-based rank inside [lo, hi)
+                double ans = h1;
+                for (int a = 0; a < n; ++a) {
+                    double v = dload(a);
+                    int less = 0, le = 0;
+                    for (int b2 = 0; b2 < n; ++b2) {
+                        double x = dload(b2);
+                        less += x < v;
+                        le += x <= v;
+                    }
+                    if (less < r && r <= le) ans = v;
+                }
+                return ans;
+            }
+            // a single representable value left in [lo, hi): it is the answer
+            if (!(nextafter(lo, INFINITY) < hi)) return lo;
+        }
+        return hi;
+    }
+
+    // Keeps the k_cap smallest (D, source index) among D < r2 in the list
+    // (called when more than k_cap sources are inside); returns the number of
+    // list entries written.
+    PCMS_HD int cap_collect(double r2)
+    {
+        const double v = kth(k_cap, 0.0, 0, r2, words / 2);
+        const double vnext = nextafter(v, INFINITY);
+        int n = 0, c_eq = 0;
+        each(vnext, [&](int p, double d2) {
+            if (d2 < v) {
+                if (n < k_cap) at(n) = p;
+                ++n;
+            } else if (d2 == v) {
+                ++c_eq;
+            }
+        });
+        const int need = k_cap - n;
+        if (need <= 0) return k_cap;
+        int jthr = 0x7fffffff;
+        if (need < c_eq) {        // ties at v: the smallest source indices win
+            int prev = -1;
+            for (int r = 0; r < need; ++r) {
+                int best = 0x7fffffff;
+                each(vnext, [&](int p, double d2) {
+                    if (d2 == v) {
+                        int j = perm[p];
+                        if (j > prev && j < best) best = j;
+                    }
+                });
+                prev = best;
+            }
+            jthr = prev;
+        }
+        each(vnext, [&](int p, double d2) {
+            if (d2 == v && perm[p] <= jthr && n < k_cap) at(n++) = p;
+        });
+        return n;
+    }
+};
+
+}  // namespace pcms

@@ -1,0 +1,242 @@
+"""Python binding of the C interface in include/pcms_mls.h.
+
+Argument marshalling only: every step of the transfer runs in the HIP
+library (libpcms_mls.so).  Tensors are passed as device pointers together
+with torch's current HIP stream.  When the library is missing this module
+raises; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcms_mls.so")
+
+PCMS_OK = 0
+PCMS_ERR_ARG = 1
+PCMS_ERR_HIP = 2
+PCMS_ERR_NOMEM = 3
+PCMS_ERR_UNDERDETERMINED = 4
+PCMS_ERR_SINGULAR = 5
+PCMS_ERR_RADIUS_EXHAUSTED = 6
+
+TGT_OK, TGT_UNDERDETERMINED, TGT_SINGULAR, TGT_RADIUS_EXHAUSTED, TGT_CAPPED = 0, 1, 2, 3, 0x10
+RADIUS_FIXED, RADIUS_KNN, RADIUS_GROW = 0, 1, 2
+WEIGHT_WENDLAND_C2, WEIGHT_C4, WEIGHT_GAUSSIAN, WEIGHT_CONST, WEIGHT_IMQ = 0, 1, 2, 3, 4
+FP64, MIXED, MIXED_REFINE = 0, 1, 2
+ASYNC = 0x1
+
+EXPORTED = ("pcms_mls_opts_default", "pcms_grid_build", "pcms_grid_free", "pcms_neighbors",
+            "pcms_mls_transfer", "pcms_mls_transfer_grid", "pcms_version", "pcms_last_error")
+
+
+class PcmsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pcms error {code}: {msg}")
+        self.code = code
+
+
+class Radius(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("k", ctypes.c_int32), ("n_min", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("r", ctypes.c_double)]
+
+
+class MlsOpts(ctypes.Structure):
+    _fields_ = [("weight", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("lam", ctypes.c_double), ("flags", ctypes.c_uint32), ("block", ctypes.c_int32),
+                ("summary", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libpcms_mls.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2510_18838_amd/build.py "
+                          "(or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    L.pcms_mls_opts_default.argtypes = [ctypes.POINTER(MlsOpts)]
+    L.pcms_mls_opts_default.restype = None
+    L.pcms_grid_build.argtypes = [P, i64, i32, P, dbl, dbl, P, ctypes.POINTER(P)]
+    L.pcms_grid_build.restype = i32
+    L.pcms_grid_free.argtypes = [P]
+    L.pcms_grid_free.restype = i32
+    L.pcms_neighbors.argtypes = [P, P, i64, ctypes.POINTER(Radius), i32, P, P, P, P, P, P]
+    L.pcms_neighbors.restype = i32
+    L.pcms_mls_transfer.argtypes = [P, i64, i32, P, i32, P, i64, i32, ctypes.POINTER(Radius), i32,
+                                    P, ctypes.POINTER(MlsOpts), P, P, P]
+    L.pcms_mls_transfer.restype = i32
+    L.pcms_mls_transfer_grid.argtypes = [P, P, i32, P, i64, i32, ctypes.POINTER(Radius), i32,
+                                         ctypes.POINTER(MlsOpts), P, P, P]
+    L.pcms_mls_transfer_grid.restype = i32
+    L.pcms_version.argtypes = []
+    L.pcms_version.restype = i32
+    L.pcms_last_error.argtypes = []
+    L.pcms_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().pcms_last_error().decode()
+
+
+def _check(code: int, allow=()):
+    if code != PCMS_OK and code not in allow:
+        raise PcmsError(code, last_error())
+    return code
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name):
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA/HIP tensor")
+    return t
+
+
+def radius(mode=RADIUS_FIXED, r=0.0, k=0, n_min=0, max_iter=40) -> Radius:
+    return Radius(int(mode), int(k), int(n_min), int(max_iter), float(r))
+
+
+def opts(weight=WEIGHT_WENDLAND_C2, precision=FP64, lam=0.0, flags=0, block=0,
+         summary: Optional[torch.Tensor] = None) -> MlsOpts:
+    o = MlsOpts()
+    lib().pcms_mls_opts_default(ctypes.byref(o))
+    o.weight, o.precision, o.lam, o.flags, o.block = weight, precision, lam, flags, block
+    o.summary = None if summary is None else summary.data_ptr()
+    return o
+
+
+def num_monomials(dim: int, degree: int) -> int:
+    return math.comb(dim + degree, degree)
+
+
+class Grid:
+    """Owning wrapper of a pcms_grid handle."""
+
+    def __init__(self, handle: ctypes.c_void_p, n_src: int, dim: int):
+        self.handle, self.n_src, self.dim = handle, n_src, dim
+
+    def free(self):
+        if self.handle:
+            lib().pcms_grid_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _host_scale(inv_scale, dim):
+    if inv_scale is None:
+        return None, None
+    arr = (ctypes.c_double * dim)(*[float(x) for x in inv_scale])
+    return arr, ctypes.cast(arr, ctypes.c_void_p)
+
+
+def pcms_grid_build(src: torch.Tensor, inv_scale=None, cell_width=0.0, pts_per_cell=0.0,
+                    stream=None) -> Grid:
+    _dev(src, torch.float64, "src")
+    n, dim = src.shape
+    keep, g = _host_scale(inv_scale, dim)
+    h = ctypes.c_void_p()
+    _check(lib().pcms_grid_build(_ptr(src), n, dim, g, float(cell_width), float(pts_per_cell),
+                                 _stream(stream), ctypes.byref(h)))
+    return Grid(h, n, dim)
+
+
+def pcms_neighbors(grid: Grid, tgt: torch.Tensor, rad: Radius, k_cap: int, stream=None,
+                   allow_status_errors=True):
+    """Returns dict(nbr [n_tgt, k_cap] int32, n_kept, n_found, r2, status, code)."""
+    _dev(tgt, torch.float64, "tgt")
+    n = tgt.shape[0]
+    dev = tgt.device
+    nbr = torch.full((n, k_cap), -1, dtype=torch.int32, device=dev)
+    n_kept = torch.zeros(n, dtype=torch.int32, device=dev)
+    n_found = torch.zeros(n, dtype=torch.int32, device=dev)
+    r2 = torch.zeros(n, dtype=torch.float64, device=dev)
+    st = torch.zeros(n, dtype=torch.uint8, device=dev)
+    allow = (PCMS_ERR_RADIUS_EXHAUSTED,) if allow_status_errors else ()
+    code = _check(lib().pcms_neighbors(grid.handle, _ptr(tgt), n, ctypes.byref(rad), int(k_cap),
+                                       _stream(stream), _ptr(nbr), _ptr(n_kept), _ptr(n_found),
+                                       _ptr(r2), _ptr(st)), allow)
+    return dict(nbr=nbr, n_kept=n_kept, n_found=n_found, r2=r2, status=st, code=code)
+
+
+_STATUS_CODES = (PCMS_ERR_UNDERDETERMINED, PCMS_ERR_SINGULAR, PCMS_ERR_RADIUS_EXHAUSTED)
+
+
+def pcms_mls_transfer(src: torch.Tensor, src_vals: torch.Tensor, tgt: torch.Tensor,
+                      basis_degree: int, rad: Radius, k_cap: int, inv_scale=None,
+                      o: Optional[MlsOpts] = None, stream=None, out: Optional[torch.Tensor] = None,
+                      status: Optional[torch.Tensor] = None, allow_status_errors=True):
+    """One-shot transfer.  Returns (tgt_vals [n_fields, n_tgt], status [n_tgt], code)."""
+    _dev(src, torch.float64, "src")
+    _dev(src_vals, torch.float64, "src_vals")
+    _dev(tgt, torch.float64, "tgt")
+    n_src, dim = src.shape
+    vals2 = src_vals if src_vals.dim() == 2 else src_vals.view(1, -1)
+    nf = vals2.shape[0]
+    n_tgt = tgt.shape[0]
+    if out is None:
+        out = torch.empty((nf, n_tgt), dtype=torch.float64, device=tgt.device)
+    if status is None:
+        status = torch.empty(n_tgt, dtype=torch.uint8, device=tgt.device)
+    keep, g = _host_scale(inv_scale, dim)
+    o = opts() if o is None else o
+    allow = _STATUS_CODES if allow_status_errors else ()
+    code = _check(lib().pcms_mls_transfer(_ptr(src), n_src, dim, _ptr(vals2), nf, _ptr(tgt), n_tgt,
+                                          int(basis_degree), ctypes.byref(rad), int(k_cap), g,
+                                          ctypes.byref(o), _stream(stream), _ptr(out),
+                                          _ptr(status)), allow)
+    return out, status, code
+
+
+def pcms_mls_transfer_grid(grid: Grid, src_vals: torch.Tensor, tgt: torch.Tensor,
+                           basis_degree: int, rad: Radius, k_cap: int,
+                           o: Optional[MlsOpts] = None, stream=None,
+                           out: Optional[torch.Tensor] = None,
+                           status: Optional[torch.Tensor] = None, allow_status_errors=True):
+    _dev(src_vals, torch.float64, "src_vals")
+    _dev(tgt, torch.float64, "tgt")
+    vals2 = src_vals if src_vals.dim() == 2 else src_vals.view(1, -1)
+    nf = vals2.shape[0]
+    n_tgt = tgt.shape[0]
+    if out is None:
+        out = torch.empty((nf, n_tgt), dtype=torch.float64, device=tgt.device)
+    if status is None:
+        status = torch.empty(n_tgt, dtype=torch.uint8, device=tgt.device)
+    o = opts() if o is None else o
+    allow = _STATUS_CODES if allow_status_errors else ()
+    code = _check(lib().pcms_mls_transfer_grid(grid.handle, _ptr(vals2), nf, _ptr(tgt), n_tgt,
+                                               int(basis_degree), ctypes.byref(rad), int(k_cap),
+                                               ctypes.byref(o), _stream(stream), _ptr(out),
+                                               _ptr(status)), allow)
+    return out, status, code
+
+
+def radius_of(prob) -> Radius:
+    """Radius spec of a synth.Problem."""
+    return radius(prob.mode, prob.radius, prob.k, prob.n_min, prob.max_iter)

@@ -1,0 +1,307 @@
+// CPU emulation of the HIP library's kernels, for indexing checks under the
+// address and undefined-behaviour sanitisers.  It runs the per-target search
+// and fit code of fit.h / search.h unchanged (compiled for the host), and the
+// grid build with the same bucket sizing, keys and radix-sort scatter pieces
+// (device_common.h), following the kernels' block/round/wave structure.
+// Every LDS word access is bounds-checked per lane.
+//
+// Usage: pcms_emu <input.bin> <output.bin>   (format written by emu_driver.py)
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "fit.h"
+
+[[noreturn]] void pcms_emu_lds_fault(int e, int words)
+{
+    std::fprintf(stderr, "LDS word %d outside the lane's %d words\n", e, words);
+    std::abort();
+}
+
+namespace {
+
+using namespace pcms;
+
+[[noreturn]] void die(const char *m)
+{
+    std::fprintf(stderr, "pcms_emu: %s\n", m);
+    std::abort();
+}
+
+struct Reader {
+    FILE *f;
+    int64_t i64()
+    {
+        int64_t v;
+        if (std::fread(&v, 8, 1, f) != 1) die("short read");
+        return v;
+    }
+    double f64()
+    {
+        double v;
+        if (std::fread(&v, 8, 1, f) != 1) die("short read");
+        return v;
+    }
+    template <class T>
+    std::vector<T> arr(size_t n)
+    {
+        std::vector<T> v(n);
+        if (n && std::fread(v.data(), sizeof(T), n, f) != n) die("short read");
+        return v;
+    }
+};
+
+constexpr int kSortThreads = 256, kSortRounds = 16, kSortItems = kSortThreads * kSortRounds;
+
+// Stable LSD radix sort with the kernels' structure: per-block digit
+// histograms (digit-major), exclusive scan, then per-block rounds of 256
+// items in 4 waves, ranked with the ballot pieces the kernel uses.
+void radix_sort_emu(std::vector<unsigned> &keys, std::vector<int> &vals, int bits)
+{
+    const int n = (int)keys.size();
+    const int nb = (n + kSortItems - 1) / kSortItems;
+    std::vector<unsigned> kout(n);
+    std::vector<int> vout(n);
+    const int passes = std::max(1, (bits + 7) / 8);
+    for (int ps = 0; ps < passes; ++ps) {
+        const int shift = 8 * ps;
+        std::vector<int> hist((size_t)256 * nb, 0);
+        for (int b = 0; b < nb; ++b)
+            for (int r = 0; r < kSortRounds; ++r)
+                for (int t = 0; t < kSortThreads; ++t) {
+                    int i = b * kSortItems + r * kSortThreads + t;
+                    if (i < n) hist[(size_t)((keys[i] >> shift) & 255) * nb + b]++;
+                }
+        int run = 0;
+        for (auto &h : hist) {
+            int c = h;
+            h = run;
+            run += c;
+        }
+        for (int b = 0; b < nb; ++b) {
+            int running[256];
+            for (int d = 0; d < 256; ++d) running[d] = hist[(size_t)d * nb + b];
+            for (int r = 0; r < kSortRounds; ++r) {
+                const int base = b * kSortItems + r * kSortThreads;
+                if (base >= n) break;
+                unsigned key[256];
+                int val[256], digit[256];
+                bool valid[256];
+                for (int t = 0; t < 256; ++t) {
+                    int i = base + t;
+                    valid[t] = i < n;
+                    key[t] = valid[t] ? keys[i] : 0u;
+                    val[t] = valid[t] ? vals[i] : 0;
+                    digit[t] = (key[t] >> shift) & 255;
+                }
+                unsigned long long vb[4] = {0, 0, 0, 0}, bb[4][8] = {};
+                for (int t = 0; t < 256; ++t) {
+                    int w = t >> 6, lane = t & 63;
+                    if (valid[t]) vb[w] |= 1ull << lane;
+                    for (int q = 0; q < 8; ++q)
+                        if ((digit[t] >> q) & 1) bb[w][q] |= 1ull << lane;
+                }
+                unsigned long long mask[256];
+                int wave_cnt[4][256];
+                std::memset(wave_cnt, 0, sizeof(wave_cnt));
+                for (int t = 0; t < 256; ++t) mask[t] = digit_match(vb[t >> 6], bb[t >> 6], digit[t]);
+                for (int t = 0; t < 256; ++t)
+                    if (valid[t] && (mask[t] & lanes_below(t & 63)) == 0)
+                        wave_cnt[t >> 6][digit[t]] = __builtin_popcountll(mask[t]);
+                for (int t = 0; t < 256; ++t) {
+                    if (!valid[t]) continue;
+                    int pos = scatter_slot(running[digit[t]], wave_cnt, t >> 6, digit[t], mask[t], t & 63);
+                    if (pos < 0 || pos >= n) die("radix scatter slot out of range");
+                    kout[pos] = key[t];
+                    vout[pos] = val[t];
+                }
+                for (int d = 0; d < 256; ++d)
+                    running[d] += wave_cnt[0][d] + wave_cnt[1][d] + wave_cnt[2][d] + wave_cnt[3][d];
+            }
+        }
+        keys.swap(kout);
+        vals.swap(vout);
+    }
+}
+
+int key_bits(int cap)
+{
+    int b = 0;
+    while (b < 31 && (1u << b) < (unsigned)cap) ++b;
+    return b;
+}
+
+template <int D, bool UNIT>
+void run_nbr(const KArgs &a, const GridParams &gp, int block)
+{
+    const int nblk = (a.n_tgt + block - 1) / block;
+    std::vector<int> lds((size_t)block * a.words);
+    for (int b = 0; b < nblk; ++b) {
+        std::fill(lds.begin(), lds.end(), 0x7f7f7f7f);
+        for (int lane = 0; lane < block; ++lane) {
+            int i = b * block + lane;
+            if (i < a.n_tgt) nbr_target<D, UNIT>(a, gp, i, lds.data(), lane, block);
+        }
+    }
+}
+
+template <int D, int P, bool MIXED, bool UNIT>
+void run_xfer(const KArgs &a, const GridParams &gp, int block)
+{
+    const int nblk = (a.n_tgt + block - 1) / block;
+    std::vector<int> lds((size_t)block * a.words);
+    for (int b = 0; b < nblk; ++b) {
+        std::fill(lds.begin(), lds.end(), 0x7f7f7f7f);
+        for (int lane = 0; lane < block; ++lane) {
+            int i = b * block + lane;
+            if (i < a.n_tgt) xfer_target<D, P, MIXED, UNIT>(a, gp, i, lds.data(), lane, block);
+        }
+    }
+}
+
+template <int D, bool UNIT>
+void dispatch(int op, const KArgs &a, const GridParams &gp, int block, int degree, bool mixed)
+{
+    if (op == 0) return run_nbr<D, UNIT>(a, gp, block);
+#define X(PP)                                                                  \
+    if (degree == PP) {                                                        \
+        if (mixed) return run_xfer<D, PP, true, UNIT>(a, gp, block);           \
+        return run_xfer<D, PP, false, UNIT>(a, gp, block);                     \
+    }
+    X(0) X(1) X(2)
+#undef X
+}
+
+}  // namespace
+
+int main(int argc, char **argv)
+{
+    if (argc != 3) die("usage: pcms_emu in.bin out.bin");
+    FILE *f = std::fopen(argv[1], "rb");
+    if (!f) die("cannot open input");
+    Reader rd{f};
+    if (rd.i64() != 0x50434d53454d55LL) die("bad magic");
+    const int op = (int)rd.i64();
+    const int64_t n_src = rd.i64(), dim = rd.i64(), n_tgt = rd.i64(), nf = rd.i64();
+    const int degree = (int)rd.i64(), mode = (int)rd.i64(), k = (int)rd.i64();
+    const int n_min = (int)rd.i64(), max_iter = (int)rd.i64(), k_cap = (int)rd.i64();
+    const int weight = (int)rd.i64(), precision = (int)rd.i64(), block = (int)rd.i64();
+    const double r = rd.f64(), lambda = rd.f64(), cell_width = rd.f64(), ppc = rd.f64();
+    double g[kMaxDim];
+    for (int q = 0; q < kMaxDim; ++q) g[q] = rd.f64();
+    auto src = rd.arr<double>((size_t)(n_src * dim));
+    auto vals = rd.arr<double>((size_t)(nf * n_src));
+    auto tgt = rd.arr<double>((size_t)(n_tgt * dim));
+    std::fclose(f);
+
+    // grid build
+    double lo[kMaxDim], hi[kMaxDim];
+    for (int q = 0; q < dim; ++q) {
+        lo[q] = INFINITY;
+        hi[q] = -INFINITY;
+        for (int64_t j = 0; j < n_src; ++j) {
+            lo[q] = std::fmin(lo[q], src[j * dim + q]);
+            hi[q] = std::fmax(hi[q], src[j * dim + q]);
+        }
+    }
+    const int cap = (int)std::min<int64_t>(2 * n_src + 64, (int64_t)1 << 30);
+    GridParams gp;
+    grid_params_compute(lo, hi, (int)dim, n_src, g, cell_width, ppc, cap, &gp);
+    if (gp.n_cells > cap) die("bucket count above the allocation");
+    std::vector<unsigned> keys(n_src);
+    std::vector<int> perm(n_src);
+    for (int64_t j = 0; j < n_src; ++j) {
+        keys[j] = bucket_key(gp, &src[j * dim]);
+        perm[j] = (int)j;
+        if (keys[j] >= (unsigned)gp.n_cells) die("bucket key out of range");
+    }
+    radix_sort_emu(keys, perm, key_bits(cap));
+    for (int64_t j = 1; j < n_src; ++j)
+        if (keys[j - 1] > keys[j] || (keys[j - 1] == keys[j] && perm[j - 1] > perm[j]))
+            die("radix sort is not stable-sorted");
+    std::vector<int> cs((size_t)cap + 1, -1);
+    for (int c = 0; c <= gp.n_cells; ++c) {
+        int l = 0, h = (int)n_src;
+        while (l < h) {
+            int mid = (l + h) >> 1;
+            if (keys[mid] < (unsigned)c) l = mid + 1;
+            else h = mid;
+        }
+        cs[c] = l;
+    }
+    // the kernels may read only [0, n_cells]: keep exactly that for the sanitiser
+    cs = std::vector<int>(cs.begin(), cs.begin() + gp.n_cells + 1);
+    std::vector<double> spts((size_t)(n_src * dim));
+    for (int64_t p = 0; p < n_src; ++p)
+        for (int q = 0; q < dim; ++q) spts[p * dim + q] = src[(size_t)perm[p] * dim + q];
+    // targets
+    std::vector<unsigned> tkeys(n_tgt);
+    std::vector<int> tperm(n_tgt);
+    for (int64_t i = 0; i < n_tgt; ++i) {
+        tkeys[i] = bucket_key(gp, &tgt[i * dim]);
+        tperm[i] = (int)i;
+    }
+    radix_sort_emu(tkeys, tperm, key_bits(cap));
+    std::vector<double> svals((size_t)(n_src * nf));
+    for (int64_t p = 0; p < n_src; ++p)
+        for (int l = 0; l < nf; ++l) svals[p * nf + l] = vals[(size_t)l * n_src + perm[p]];
+
+    KArgs a{};
+    a.gp = &gp;
+    a.cs = cs.data();
+    a.spts = spts.data();
+    a.perm = perm.data();
+    a.tgt = tgt.data();
+    a.tperm = tperm.data();
+    a.n_tgt = (int)n_tgt;
+    a.mode = mode;
+    a.k = k;
+    a.n_min = n_min;
+    a.max_iter = max_iter;
+    a.r = r;
+    a.k_cap = k_cap;
+    a.words = k_cap < 2 ? 2 : k_cap;
+    a.svals = svals.data();
+    a.nf = (int)nf;
+    a.weight = weight;
+    a.refine = precision == PCMS_MIXED_REFINE;
+    a.lambda = lambda;
+    std::vector<double> out((size_t)(nf * n_tgt), 0.0);
+    std::vector<int32_t> nbr((size_t)(n_tgt * k_cap), -1), n_kept(n_tgt), n_found(n_tgt);
+    std::vector<double> r2(n_tgt);
+    std::vector<uint8_t> status(n_tgt);
+    a.out = out.data();
+    a.nbr = nbr.data();
+    a.n_kept = n_kept.data();
+    a.n_found = n_found.data();
+    a.r2 = r2.data();
+    a.status = status.data();
+    bool unit = true;
+    for (int q = 0; q < dim; ++q) unit = unit && g[q] == 1.0;
+    const bool mixed = precision != PCMS_FP64;
+#define DIMCASE(DD)                                                                 \
+    case DD:                                                                        \
+        if (unit) dispatch<DD, true>(op, a, gp, block, degree, mixed);              \
+        else dispatch<DD, false>(op, a, gp, block, degree, mixed);                  \
+        break;
+    switch (dim) {
+        DIMCASE(1) DIMCASE(2) DIMCASE(3) DIMCASE(4) DIMCASE(5)
+        default: die("bad dim");
+    }
+#undef DIMCASE
+    FILE *o = std::fopen(argv[2], "wb");
+    if (!o) die("cannot open output");
+    if (op == 0) {
+        std::fwrite(nbr.data(), 4, nbr.size(), o);
+        std::fwrite(n_kept.data(), 4, n_kept.size(), o);
+        std::fwrite(n_found.data(), 4, n_found.size(), o);
+        std::fwrite(r2.data(), 8, r2.size(), o);
+    } else {
+        std::fwrite(out.data(), 8, out.size(), o);
+    }
+    std::fwrite(status.data(), 1, status.size(), o);
+    std::fclose(o);
+    return 0;
+}

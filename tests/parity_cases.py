@@ -1,0 +1,228 @@
+"""Parity cases shared by the GPU tests and the CPU emulation tests.
+
+A backend provides neighbors(prob) and transfer(prob, precision, weight, lam,
+block) returning the same dicts as the oracle wrapper; every case compares
+it with the FP64 CPU oracle on seeded inputs.
+
+Bars: neighbour lists, counts, squared radii and statuses bit-exact; values
+within TOL (max over fields of the inf-norm error over valid targets,
+relative to the field's inf-norm: Eq. 2's accuracy error read with the
+inf-norm), plus a per-target conditioning term COND * kappa.  MIXED_REFINE is
+the mixed-precision mode held to 1e-6; MIXED without refinement is held to
+1e-4 + 100 u32 kappa (its error grows with the conditioning of the FP32
+moment matrix).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle
+from paper_2510_18838_amd import synth
+
+FP64, MIXED, MIXED_REFINE = 0, 1, 2
+TOL = {FP64: 1e-10, MIXED_REFINE: 1e-6, MIXED: 1e-4}
+# rounding of the normal equations grows with their conditioning: 1000 u64
+# for FP64 and refined mixed, 100 u32 for unrefined FP32 assembly
+COND = {FP64: 1e3 * 1.1e-16, MIXED_REFINE: 1e3 * 1.1e-16, MIXED: 100 * 6e-8}
+CAPPED = 0x10
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def compare_lists(got, ref, where=""):
+    for key in ("n_kept", "n_found", "status"):
+        bad = np.nonzero(got[key] != ref[key])[0]
+        assert bad.size == 0, (f"{where}: {key} differs at {bad[:5]}: "
+                               f"got {got[key][bad[:5]]} ref {ref[key][bad[:5]]}")
+    bad = np.nonzero(got["r2"] != ref["r2"])[0]
+    assert bad.size == 0, f"{where}: r2 differs at {bad[:5]}"
+    for i in range(len(ref["n_kept"])):
+        n = ref["n_kept"][i]
+        if not np.array_equal(got["nbr"][i, :n], ref["nbr"][i, :n]):
+            raise AssertionError(f"{where}: list of target {i} differs")
+
+
+def rel_err(got, ref, mask):
+    """max over fields of ||got - ref||_inf / ||ref||_inf over the targets in mask."""
+    if not mask.any():
+        return 0.0
+    worst = 0.0
+    for l in range(ref.shape[0]):
+        den = np.abs(ref[l, mask]).max()
+        num = np.abs(got[l, mask] - ref[l, mask]).max()
+        worst = max(worst, num / den)
+    return worst
+
+
+def check_lists(be, prob, where, brute=False):
+    ref = oracle.neighbors(prob.src, prob.tgt, brute=brute, **oracle.problem_kwargs(prob))
+    compare_lists(be.neighbors(prob), ref, where)
+    return ref
+
+
+def check_transfer(be, prob, where, precisions=(FP64, MIXED_REFINE, MIXED), weight=0, lam=0.0):
+    ref = oracle.transfer(prob.src, prob.vals, prob.tgt, prob.degree, weight_kind=weight, lam=lam,
+                          **oracle.problem_kwargs(prob))
+    ok = (ref["status"] & 0xF) == 0
+    errs = {}
+    for prec in precisions:
+        r = be.transfer(prob, prec, weight=weight, lam=lam)
+        got, st = r["out"], r["status"]
+        bad = np.nonzero(st != ref["status"])[0]
+        # statuses may differ only where the oracle's smallest Cholesky pivot
+        # is near the singularity threshold (FP64) or beyond FP32 reach (mixed)
+        limit = 1e-11 if prec == FP64 else 1e-5
+        assert all(ref["pivot_ratio"][i] < limit for i in bad), \
+            f"{where}: status differs at {bad[:5]}: {st[bad[:5]]} vs {ref['status'][bad[:5]]}"
+        mask = ok & (st == ref["status"])
+        assert np.isfinite(got[:, mask]).all(), f"{where}: non-finite values"
+        assert np.isnan(got[:, (st & 0xF) != 0]).all(), f"{where}: failed targets not NaN"
+        e = rel_err(got, ref["out"], mask)
+        errs[prec] = e
+        # per target: TOL plus a conditioning term, kappa ~ 1 / (smallest
+        # Cholesky pivot / largest diagonal entry) of the oracle's moment matrix
+        kappa = 1.0 / np.maximum(ref["pivot_ratio"][mask], 1e-300)
+        scale = np.abs(ref["out"][:, mask]).max(axis=1, keepdims=True)
+        dev = (np.abs(got[:, mask] - ref["out"][:, mask]) / scale).max(axis=0)
+        bound = TOL[prec] + COND[prec] * kappa
+        well = kappa < 1e6
+        e_well = float(dev[well].max()) if well.any() else 0.0
+        say(f"{where} precision={prec}: max rel err {e:.3e} over {int(mask.sum())} targets, "
+            f"{e_well:.3e} over the {int(well.sum())} with kappa < 1e6")
+        worst = np.argmax(dev - bound) if dev.size else 0
+        assert (dev <= bound).all(), (f"{where}: precision {prec} error {dev[worst]:.3e} above "
+                                      f"{bound[worst]:.3e} (kappa {kappa[worst]:.2e})")
+    return errs
+
+
+def custom(src, vals, tgt, degree, mode, **kw):
+    vals = np.atleast_2d(vals)
+    return synth.Problem("custom", np.ascontiguousarray(src, dtype=np.float64),
+                         np.ascontiguousarray(vals, dtype=np.float64),
+                         np.ascontiguousarray(tgt, dtype=np.float64), degree=degree, mode=mode,
+                         **kw)
+
+
+# ---------------------------------------------------------------------------
+# cases
+# ---------------------------------------------------------------------------
+
+def case_c1(be):
+    p = synth.c1()
+    ref = check_lists(be, p, "c1", brute=True)
+    assert (ref["status"] & CAPPED).sum() > 10         # the cap path is exercised
+    check_transfer(be, p, "c1")
+
+
+def scaled(name, small=False):
+    if name == "c2":
+        return synth.c2(n_side=60 if small else 150, n_tgt=2011 if small else 20011)
+    if name == "c3":
+        return synth.c3(n_src=15000 if small else 60000, n_tgt=2013 if small else 20013,
+                        n_fields=3 if small else 8)
+    if name == "c5":
+        return synth.c5(n=12000 if small else 40000, n_tgt=2007 if small else 15007)
+    raise KeyError(name)
+
+
+def case_scaled(be, name, small=False):
+    p = scaled(name, small)
+    say(f"{name}: n_src={p.src.shape[0]} n_tgt={p.tgt.shape[0]} dim={p.dim}")
+    check_lists(be, p, name)
+    check_transfer(be, p, name)
+
+
+def case_c4(be, n=8, size_scale=0.05):
+    for b in range(n):
+        p = synth.c4_problem(b, size_scale=size_scale)
+        say(f"c4 problem {b}: n_src={p.src.shape[0]} n_tgt={p.tgt.shape[0]} d={p.dim} "
+            f"p={p.degree} nf={p.n_fields}")
+        check_lists(be, p, f"c4[{b}]")
+        check_transfer(be, p, f"c4[{b}]")
+
+
+DIM_CASES = [(1, 2, synth.KNN), (1, 1, synth.FIXED), (4, 1, synth.KNN), (4, 2, synth.GROW),
+             (2, 0, synth.FIXED), (3, 0, synth.KNN), (5, 2, synth.KNN)]
+
+
+def case_dims(be, dim, degree, mode, scale=1.0):
+    m = math.comb(dim + degree, degree)
+    n_src = int((6000 if dim < 5 else 20000) * scale)
+    kw = dict(radius=(0.02 if dim == 1 else 0.15), k=2 * m + 3, n_min=2 * m, k_cap=max(3 * m, 8))
+    p = synth.uniform_problem(7 + dim * 3 + degree, n_src, int(3001 * scale), dim, degree, mode,
+                              n_fields=3, **kw)
+    check_lists(be, p, f"d{dim}p{degree}")
+    check_transfer(be, p, f"d{dim}p{degree}m{mode}")
+
+
+def case_weight(be, weight):
+    p = synth.uniform_problem(31, 5000, 2000, 2, 2, synth.KNN, n_fields=2, k=20, k_cap=32)
+    check_transfer(be, p, f"weight {weight}", precisions=(FP64, MIXED_REFINE), weight=weight)
+
+
+def case_tikhonov(be, lam):
+    p = synth.uniform_problem(32, 5000, 2000, 3, 2, synth.KNN, n_fields=2, k=25, k_cap=32)
+    check_transfer(be, p, f"lambda {lam}", precisions=(FP64, MIXED_REFINE), lam=lam)
+
+
+def case_far_targets(be):
+    rng = np.random.default_rng(3)
+    src = rng.uniform(0, 1, (500, 2))
+    vals = rng.standard_normal(500)
+    tgt = np.array([[0.5, 0.5], [7.0, -3.0], [1.02, 0.5]])
+    for t in (tgt[:1], tgt):
+        p = custom(src, vals, t, 1, synth.FIXED, radius=0.1, k_cap=64)
+        check_transfer(be, p, f"far fixed {len(t)}")
+        r = be.transfer(p, FP64)
+        if len(t) > 1:
+            assert r["status"][1] == 1
+    p = custom(src, vals, tgt, 2, synth.KNN, k=12, k_cap=16)
+    check_lists(be, p, "far knn")
+    check_transfer(be, p, "far knn")
+
+
+def case_singular_exhausted(be):
+    x = np.linspace(0, 1, 64)
+    line = np.stack([x, np.full_like(x, 0.5)], 1)
+    p = custom(line, x, np.array([[0.5, 0.5], [0.25, 0.5]]), 2, synth.FIXED, radius=0.3, k_cap=64)
+    for prec in (FP64, MIXED_REFINE):
+        r = be.transfer(p, prec)
+        assert (r["status"] == 2).all() and np.isnan(r["out"]).all(), (prec, r["status"])
+    rng = np.random.default_rng(5)
+    src = rng.uniform(0, 1, (300, 2))
+    p = custom(src, src[:, 0], np.array([[0.5, 0.5], [0.2, 0.7]]), 1, synth.GROW, radius=1e-4,
+               n_min=10, max_iter=0, k_cap=32)
+    r = be.transfer(p, FP64)
+    assert (r["status"] == 3).all()
+    p.max_iter = 40
+    check_lists(be, p, "grow")
+    check_transfer(be, p, "grow")
+
+
+def case_ties(be):
+    g1 = np.arange(9) * 0.125
+    lat = np.stack(np.meshgrid(g1, g1, indexing="ij"), -1).reshape(-1, 2)
+    src = np.concatenate([lat, lat[::3]])                  # exact ties and duplicates
+    tgt = np.concatenate([lat[::5], lat[::7] + 0.0625])
+    for mode, kw in [(synth.FIXED, dict(radius=0.25, k_cap=6)), (synth.KNN, dict(k=9, k_cap=5)),
+                     (synth.KNN, dict(k=13, k_cap=40)),
+                     (synth.GROW, dict(radius=0.1, n_min=11, k_cap=7))]:
+        p = custom(src, src[:, 0] + 2 * src[:, 1], tgt, 1, mode, **kw)
+        check_lists(be, p, f"ties {mode} {kw}", brute=True)
+    same = np.full((50, 3), 0.25)                          # one bucket, all distances tie
+    p = custom(same, np.ones(50), np.array([[0.25, 0.25, 0.25], [0.3, 0.2, 0.1]]), 0,
+               synth.KNN, k=10, k_cap=16)
+    check_lists(be, p, "coincident", brute=True)
+
+
+def case_tight_caps(be):
+    p = synth.uniform_problem(41, 3000, 1500, 2, 2, synth.FIXED, n_fields=1, radius=0.08, k_cap=6)
+    check_lists(be, p, "k_cap = m")
+    check_transfer(be, p, "k_cap = m")
+    p.k_cap, p.degree = 1, 0
+    check_lists(be, p, "k_cap = 1")
+    check_transfer(be, p, "k_cap = 1")

@@ -1,0 +1,68 @@
+"""The kernels' per-target code and grid-build pieces, compiled for the CPU
+with the address and undefined-behaviour sanitisers, against the oracle.
+
+Same cases and bars as the GPU parity tests (tests/parity_cases.py), at
+smaller sizes.  This checks indexing and logic without a GPU.
+"""
+import pytest
+
+import emu_driver
+import parity_cases as C
+from paper_2510_18838_amd import synth
+
+
+class EmuBackend:
+    def neighbors(self, prob):
+        return emu_driver.run(prob, 0)
+
+    def transfer(self, prob, precision, weight=0, lam=0.0, block=64):
+        return emu_driver.run(prob, 1, precision=precision, weight=weight, lam=lam, block=block)
+
+
+BE = EmuBackend()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    emu_driver.build()
+
+
+def test_emu_c1():
+    C.case_c1(BE)
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c5"])
+def test_emu_scaled(name):
+    C.case_scaled(BE, name, small=True)
+
+
+def test_emu_c4():
+    C.case_c4(BE, n=6, size_scale=0.02)
+
+
+@pytest.mark.parametrize("dim,degree,mode", C.DIM_CASES)
+def test_emu_dims(dim, degree, mode):
+    C.case_dims(BE, dim, degree, mode, scale=0.3)
+
+
+@pytest.mark.parametrize("weight", [1, 2, 3, 4])
+def test_emu_weights(weight):
+    C.case_weight(BE, weight)
+
+
+def test_emu_tikhonov():
+    C.case_tikhonov(BE, 0.5)
+
+
+def test_emu_edge_cases():
+    C.case_far_targets(BE)
+    C.case_singular_exhausted(BE)
+    C.case_ties(BE)
+    C.case_tight_caps(BE)
+
+
+def test_emu_block_shapes():
+    p = synth.c1()
+    a = BE.transfer(p, 0, block=64)
+    b = BE.transfer(p, 0, block=256)
+    assert (a["status"] == b["status"]).all()

@@ -1,0 +1,110 @@
+"""GPU parity: the HIP path through the C interface against the FP64 CPU oracle.
+
+Cases and bars are in tests/parity_cases.py (lists bit-exact; FP64 values
+within 1e-10, MIXED_REFINE within 1e-6).
+"""
+import numpy as np
+import pytest
+import torch
+
+import parity_cases as C
+from gpu_helpers import dev, gpu_neighbors, gpu_transfer
+from paper_2510_18838_amd import pcms
+
+pytestmark = pytest.mark.gpu
+
+
+class GpuBackend:
+    def neighbors(self, prob):
+        return gpu_neighbors(prob)
+
+    def transfer(self, prob, precision, weight=0, lam=0.0, block=0):
+        out, st, _ = gpu_transfer(prob, precision, weight=weight, lam=lam, block=block)
+        return dict(out=out, status=st)
+
+
+BE = GpuBackend()
+
+
+def test_c1():
+    C.case_c1(BE)
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c5"])
+def test_scaled(name):
+    C.case_scaled(BE, name)
+
+
+def test_c4_problems_scaled():
+    C.case_c4(BE)
+
+
+@pytest.mark.parametrize("dim,degree,mode", C.DIM_CASES)
+def test_other_dimensions_and_degrees(dim, degree, mode):
+    C.case_dims(BE, dim, degree, mode)
+
+
+@pytest.mark.parametrize("weight", [pcms.WEIGHT_C4, pcms.WEIGHT_GAUSSIAN, pcms.WEIGHT_CONST,
+                                    pcms.WEIGHT_IMQ])
+def test_weight_variants(weight):
+    C.case_weight(BE, weight)
+
+
+@pytest.mark.parametrize("lam", [1e-3, 0.5])
+def test_tikhonov(lam):
+    C.case_tikhonov(BE, lam)
+
+
+def test_far_targets():
+    C.case_far_targets(BE)
+
+
+def test_singular_and_exhausted():
+    C.case_singular_exhausted(BE)
+    p = C.custom(np.stack([np.linspace(0, 1, 64), np.full(64, 0.5)], 1), np.linspace(0, 1, 64),
+                 np.array([[0.5, 0.5]]), 2, 0, radius=0.3, k_cap=64)
+    _, _, code = gpu_transfer(p)
+    assert code == pcms.PCMS_ERR_SINGULAR
+
+
+def test_ties_duplicates_degenerate_grid():
+    C.case_ties(BE)
+
+
+def test_tight_caps():
+    C.case_tight_caps(BE)
+
+
+def test_prebuilt_grid_matches_one_shot():
+    p = C.scaled("c3")
+    g = pcms.pcms_grid_build(dev(p.src), pts_per_cell=4.0)
+    out, st, _ = pcms.pcms_mls_transfer_grid(g, dev(p.vals), dev(p.tgt), p.degree,
+                                             pcms.radius_of(p), p.k_cap)
+    torch.cuda.synchronize()
+    a = out.cpu().numpy()
+    b, st2, _ = gpu_transfer(p)
+    np.testing.assert_array_equal(st.cpu().numpy(), st2)
+    assert C.rel_err(a, b, st2 == 0) <= 1e-12
+    g.free()
+
+
+def test_run_twice_bit_identical():
+    p = C.scaled("c3")
+    for prec in (pcms.FP64, pcms.MIXED_REFINE):
+        a, sa, _ = gpu_transfer(p, prec)
+        b, sb, _ = gpu_transfer(p, prec)
+        np.testing.assert_array_equal(sa, sb)
+        assert np.array_equal(a, b, equal_nan=True)
+    x = gpu_neighbors(p)
+    y = gpu_neighbors(p)
+    for k in x:
+        assert np.array_equal(x[k], y[k])
+
+
+def test_block_sizes_agree():
+    p = C.scaled("c2")
+    base, st, _ = gpu_transfer(p, pcms.FP64)
+    for block in (128, 256):
+        got, st2, _ = gpu_transfer(p, pcms.FP64, block=block)
+        np.testing.assert_array_equal(st, st2)
+        assert np.array_equal(got, base, equal_nan=True)
