@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the MLS point-cloud field transfer on one MI355X.
+
+Metric: target points per second of the 3-D quadratic transfer (mixed
+precision vs FP64) on the 4M x 4M Gaussian-mixture workload: 4*10^6 sources
+(8-component mixture, 10x density contrast), 4*10^6 uniform targets,
+quadratic basis (m = 10), radius = distance to the 40th nearest source,
+neighbour cap 64, eight fields.  One step is one whole transfer: grid build,
+target ordering, field gather, search, moment assembly, Cholesky solve and
+evaluation, with inputs already resident in HBM.
+
+Prints one JSON line with the contract's fields plus:
+  roofline      the search-and-fit kernel (the dominant one): algorithmic
+                flops per launch / its event-timed average duration, against
+                the VALU peak (ALU-bound path)
+  cpu_baseline  the FP64 CPU oracle timed on a bounded sample of the same
+                workload on the host cores
+  fp64          the same steps with the plain FP64 path, for the comparison
+  accuracy      max relative error of the headline path vs FP64 (all
+                targets) and vs the oracle (the sampled targets)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "target pts/sec, 3D quadratic MLS transfer: mixed vs FP64 at ≤1e-6 rel err"
+# VALU peak: 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.  FP32 and
+# FP64 vector FMA issue at the same rate; packed FP32 is not used.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Algorithmic flops per target of the search-and-fit kernel (3-D quadratic,
+# kNN-40 radius, 39 weighted neighbours), see the design notes:
+#   moment assembly  39 x (10 weighted monomials + 55 FMAs of G) = 39 x 120
+#   shape functions  39 x (10 FMAs p.y + 1 + 8 field FMAs)        = 39 x 38
+#   solve            Cholesky m^3/3 + two triangular solves 2 m^2 ~ 530
+#   search           exact FP64 distance (3 sub, 3 FMA) for the 6.4 x 39
+#                    candidates of a one-radius bucket stencil     = 250 x 9
+ALG_FLOPS_PER_TARGET = 39 * 120 + 39 * 38 + 530 + 250 * 9
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_digest():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2510_18838_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_digest):
+    """HBM traffic per launch from the committed counter summary, if it was
+    taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic_c3.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        t = json.load(fh)
+    if t.get("source_digest") != kernel_digest:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["mixed", "mixed_refine", "fp64"], default="mixed_refine")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (profiling aid)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the design notes for how the transfer would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2510_18838_amd import pcms, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    pcms.lib()
+    dev = torch.device("cuda:0")
+    n = int(4_000_000 * args.scale)
+    t0 = time.time()
+    p = synth.c3(n_src=n)
+    log(f"workload generated in {time.time() - t0:.1f}s: n_src={p.src.shape[0]} "
+        f"n_tgt={p.tgt.shape[0]} fields={p.n_fields}")
+    src = torch.from_numpy(p.src).to(dev)
+    vals = torch.from_numpy(p.vals).to(dev)
+    tgt = torch.from_numpy(p.tgt).to(dev)
+    M = tgt.shape[0]
+    out = torch.empty((p.n_fields, M), dtype=torch.float64, device=dev)
+    st = torch.empty(M, dtype=torch.uint8, device=dev)
+    rad = pcms.radius_of(p)
+    prec = {"mixed": pcms.MIXED, "mixed_refine": pcms.MIXED_REFINE, "fp64": pcms.FP64}[args.precision]
+
+    def run(precision, steps, warmup, out_t):
+        o = pcms.opts(precision=precision, flags=pcms.PROFILE)
+        for _ in range(warmup):
+            pcms.pcms_mls_transfer(src, vals, tgt, p.degree, rad, p.k_cap, o=o, out=out_t, status=st)
+        torch.cuda.synchronize()
+        phases = []
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            pcms.pcms_mls_transfer(src, vals, tgt, p.degree, rad, p.k_cap, o=o, out=out_t, status=st)
+            phases.append(pcms.last_phase_ms())
+        torch.cuda.synchronize()
+        t_end = time.perf_counter()
+        ms = (t_end - t_start) * 1e3 / steps
+        avg = {k: float(np.mean([ph[k] for ph in phases])) for k in phases[0]}
+        return ms, avg
+
+    log(f"timing {args.steps} steps ({args.warmup} warm-up), precision {args.precision}")
+    ms, phases = run(prec, args.steps, args.warmup, out)
+    log(f"{ms:.3f} ms/step, phases {phases}")
+    value = M / (ms / 1e3)
+    head_out = out.clone()
+    status = st.cpu().numpy()
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "target pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == pcms.FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "3-D quadratic MLS transfer, 4M Gaussian-mixture sources (10x density "
+                        "contrast) -> 4M uniform targets, kNN-40 radius, k_cap 64, 8 fields",
+            "n_src": int(p.src.shape[0]), "n_tgt": int(M), "basis_degree": p.degree,
+            "n_fields": p.n_fields, "precision": args.precision,
+        },
+        "phases_ms": phases,
+    }
+
+    kernel_ms = phases["search_fit"]
+    achieved = ALG_FLOPS_PER_TARGET * M / (kernel_ms * 1e-3) / 1e12
+    result["roofline"] = {
+        "bound": "alu",
+        "kernel": "k_transfer (search + moment assembly + Cholesky + evaluation)",
+        "achieved": achieved,
+        "peak": VALU_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / VALU_PEAK_TFLOPS,
+        "traffic": load_traffic(source_digest()),
+        "alg_flops_per_target": ALG_FLOPS_PER_TARGET,
+        "kernel_ms": kernel_ms,
+    }
+
+    if not args.no_fp64 and prec != pcms.FP64:
+        out64 = torch.empty_like(out)
+        ms64, ph64 = run(pcms.FP64, args.steps, 1, out64)
+        ok = torch.from_numpy((status & 0xF) == 0).to(dev)
+        err = 0.0
+        for l in range(p.n_fields):
+            ref = out64[l][ok]
+            err = max(err, float((head_out[l][ok] - ref).abs().max() / ref.abs().max()))
+        result["fp64"] = {"value": M / (ms64 / 1e3), "ms_per_step": ms64, "phases_ms": ph64,
+                          "mixed_speedup": ms64 / ms}
+        result["accuracy"] = {"max_rel_err_vs_fp64_all_targets": err}
+        log(f"fp64 {ms64:.3f} ms/step; headline vs fp64 max rel err {err:.3e}")
+
+    if not args.no_cpu:
+        import oracle
+        threads = oracle.max_threads()
+        # size the sample from a short probe so the timed CPU leg takes ~cpu_seconds
+        probe = min(20000, M)
+        t0 = time.time()
+        oracle.transfer(p.src, p.vals, p.tgt[:probe], p.degree, **oracle.problem_kwargs(p))
+        rate = probe / max(time.time() - t0, 1e-3)
+        sample = int(min(M, max(probe, rate * args.cpu_seconds)))
+        t0 = time.time()
+        ref = oracle.transfer(p.src, p.vals, p.tgt[:sample], p.degree, **oracle.problem_kwargs(p))
+        dt = time.time() - t0
+        result["cpu_baseline"] = {
+            "value": sample / dt, "unit": "target pts/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {p.src.shape[0]} sources (its own grid build included), "
+                      f"the first {sample} of {M} targets, FP64, {dt:.1f}s",
+        }
+        got = head_out[:, :sample].cpu().numpy()
+        ok = ((ref["status"] & 0xF) == 0) & (status[:sample] == ref["status"])
+        err = max(float(np.abs(got[l, ok] - ref["out"][l, ok]).max() / np.abs(ref["out"][l, ok]).max())
+                  for l in range(p.n_fields))
+        result.setdefault("accuracy", {})["max_rel_err_vs_oracle_sample"] = err
+        log(f"cpu oracle: {sample} targets in {dt:.1f}s on {threads} threads; "
+            f"headline vs oracle max rel err {err:.3e}")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -99,19 +99,22 @@ typedef struct {
  *   FP64:         everything in FP64.
  *   MIXED:        weights and the moment matrix G = P^T W P in FP32 with FP32
  *                 accumulation; Cholesky, solve and evaluation in FP64.
- *   MIXED_REFINE: MIXED plus one FP64 iterative-refinement step of the
- *                 shape functional G^{-1} e_0 (residual formed in FP64). */
+ *   MIXED_REFINE: MIXED plus FP64 iterative refinement of the shape
+ *                 functional G^{-1} e_0 (residual formed in FP64 from the
+ *                 same per-neighbour data): one step, up to four for
+ *                 ill-conditioned targets. */
 #define PCMS_FP64 0
 #define PCMS_MIXED 1
 #define PCMS_MIXED_REFINE 2
 
-#define PCMS_ASYNC 0x1u /* return after enqueue; statuses land in opts.summary */
+#define PCMS_ASYNC 0x1u   /* return after enqueue; statuses land in opts.summary */
+#define PCMS_PROFILE 0x2u /* time the phases with HIP events (see pcms_last_phase_ms) */
 
 typedef struct {
     int32_t weight;           /* PCMS_WEIGHT_* */
     int32_t precision;        /* PCMS_FP64 / PCMS_MIXED / PCMS_MIXED_REFINE */
     double lambda;            /* Tikhonov parameter of Eq. 1, >= 0, in the radius-scaled basis */
-    uint32_t flags;           /* PCMS_ASYNC */
+    uint32_t flags;           /* PCMS_ASYNC | PCMS_PROFILE */
     int32_t block;            /* targets per workgroup: 0 = library choice, else 64/128/256 */
     int32_t *summary;         /* device int32[4] or NULL: counts of statuses 1, 2, 3 and CAPPED */
 } pcms_mls_opts;
@@ -165,6 +168,14 @@ pcms_status pcms_mls_transfer_grid(const pcms_grid *grid, const double *src_vals
                                    const pcms_radius *radius, int32_t k_cap,
                                    const pcms_mls_opts *opts, pcms_stream_t stream,
                                    double *tgt_vals, uint8_t *status);
+
+/* Phase times in milliseconds of the calling thread's last call made with
+ * PCMS_PROFILE, measured with HIP events on that call's stream: [0] grid
+ * build, [1] target ordering, [2] field gather into bucket order, [3] the
+ * search-and-fit kernel.  Writes min(n, 4) entries to the host array `ms`
+ * and returns that count (0 if no profiled call was made).  A profiled call
+ * synchronises its stream before returning. */
+int32_t pcms_last_phase_ms(float *ms, int32_t n);
 
 /* Library version (major*10000 + minor*100 + patch) and the calling
  * thread's last error message ("" if none). */

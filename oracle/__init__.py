@@ -63,6 +63,8 @@ def lib():
         L.orc_weight.restype = ctypes.c_double
         L.orc_num_monomials.argtypes = [ctypes.c_int, ctypes.c_int]
         L.orc_num_monomials.restype = ctypes.c_int
+        L.orc_max_threads.argtypes = []
+        L.orc_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -81,6 +83,10 @@ def radius(mode, r=0.0, k=0, n_min=0, max_iter=40):
 
 def weight(kind: int, q: float) -> float:
     return lib().orc_weight(int(kind), float(q))
+
+
+def max_threads() -> int:
+    return lib().orc_max_threads()
 
 
 def num_monomials(dim: int, degree: int) -> int:

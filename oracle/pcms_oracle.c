@@ -593,3 +593,13 @@ int orc_transfer(const double *src, int64_t n_src, int dim, const double *g_in, 
 }
 
 int orc_version(void) { return 1; }
+
+/* Threads an OpenMP region of this library uses by default. */
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

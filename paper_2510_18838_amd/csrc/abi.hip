@@ -133,6 +133,48 @@ pcms_status finish(const int32_t *summary_dev, bool async, hipStream_t s, bool j
 
 std::once_flag g_pool_once[64];
 
+// Phase timing with HIP events (PCMS_PROFILE).
+constexpr int kPhases = 4;
+struct Profiler {
+    bool on = false;
+    hipStream_t s = nullptr;
+    hipEvent_t ev[kPhases + 1] = {};
+    bool have[kPhases + 1] = {};
+    pcms_status mark(int i)
+    {
+        if (!on) return PCMS_OK;
+        if (!ev[i]) PCMS_HIP(hipEventCreate(&ev[i]));
+        PCMS_HIP(hipEventRecord(ev[i], s));
+        have[i] = true;
+        return PCMS_OK;
+    }
+};
+thread_local Profiler g_prof;
+thread_local float g_phase_ms[kPhases] = {0, 0, 0, 0};
+thread_local int g_phase_n = 0;
+
+pcms_status profile_begin(const pcms_mls_opts *o, hipStream_t s)
+{
+    g_prof.on = o && (o->flags & PCMS_PROFILE);
+    g_prof.s = s;
+    for (bool &h : g_prof.have) h = false;
+    return g_prof.mark(0);
+}
+
+pcms_status profile_end()
+{
+    if (!g_prof.on) return PCMS_OK;
+    PCMS_HIP(hipEventSynchronize(g_prof.ev[kPhases]));
+    for (int i = 0; i < kPhases; ++i) {
+        float ms = 0.0f;
+        if (g_prof.have[i] && g_prof.have[i + 1]) PCMS_HIP(hipEventElapsedTime(&ms, g_prof.ev[i], g_prof.ev[i + 1]));
+        g_phase_ms[i] = ms;
+    }
+    g_phase_n = kPhases;
+    g_prof.on = false;
+    return PCMS_OK;
+}
+
 }  // namespace
 
 void set_error(const std::string &msg) { g_last_error = msg; }
@@ -182,6 +224,14 @@ void pcms_mls_opts_default(pcms_mls_opts *o)
 }
 
 int32_t pcms_version(void) { return 100; }
+
+int32_t pcms_last_phase_ms(float *ms, int32_t n)
+{
+    if (!ms || n <= 0) return 0;
+    int c = n < g_phase_n ? n : g_phase_n;
+    for (int i = 0; i < c; ++i) ms[i] = g_phase_ms[i];
+    return c;
+}
 
 const char *pcms_last_error(void) { return g_last_error.c_str(); }
 
@@ -289,12 +339,17 @@ static pcms_status transfer_common(const Grid *g, const double *src_vals, int32_
     int *tperm = (int *)((char *)sc.p + off_tperm);
     double *svals = (double *)((char *)sc.p + off_svals);
     if ((st = zero_ints(summary, 4, s)) != PCMS_OK) return st;
+    if ((st = g_prof.mark(1)) != PCMS_OK) return st;
     if ((st = sort_targets(g, tgt, n_tgt, tperm, s)) != PCMS_OK) return st;
+    if ((st = g_prof.mark(2)) != PCMS_OK) return st;
     if ((st = gather_values(g, src_vals, n_fields, svals, s)) != PCMS_OK) return st;
+    if ((st = g_prof.mark(3)) != PCMS_OK) return st;
     LaunchSpec ls{g, tgt, tperm, n_tgt, *radius, k_cap, o.block, summary};
     st = launch_transfer(ls, svals, n_fields, degree, o.weight, o.precision, o.lambda, tgt_vals,
                          status, s);
     if (st != PCMS_OK) return st;
+    if ((st = g_prof.mark(4)) != PCMS_OK) return st;
+    if ((st = profile_end()) != PCMS_OK) return st;
     return finish(summary, async, s, true);
 }
 
@@ -330,6 +385,7 @@ pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, con
     if ((st = check_scale(inv_scale, dim)) != PCMS_OK) return st;
     if (n_tgt == 0) return PCMS_OK;
     hipStream_t s = (hipStream_t)stream;
+    if ((st = profile_begin(opts, s)) != PCMS_OK) return st;
     double cw, ppc;
     cell_spec(radius, dim, &cw, &ppc);
     // one-shot grid in stream-ordered scratch
@@ -367,6 +423,8 @@ pcms_status pcms_mls_transfer_grid(const pcms_grid *grid, const double *src_vals
                                          basis_degree, radius, k_cap, opts, tgt_vals);
     if (st != PCMS_OK) return st;
     if (n_tgt == 0) return PCMS_OK;
+    if ((st = profile_begin(opts, (hipStream_t)stream)) != PCMS_OK) return st;
+    if ((st = g_prof.mark(1)) != PCMS_OK) return st;   // no grid build in this call
     return transfer_common(g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts,
                            (hipStream_t)stream, tgt_vals, status);
 }

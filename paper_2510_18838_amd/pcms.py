@@ -30,9 +30,11 @@ RADIUS_FIXED, RADIUS_KNN, RADIUS_GROW = 0, 1, 2
 WEIGHT_WENDLAND_C2, WEIGHT_C4, WEIGHT_GAUSSIAN, WEIGHT_CONST, WEIGHT_IMQ = 0, 1, 2, 3, 4
 FP64, MIXED, MIXED_REFINE = 0, 1, 2
 ASYNC = 0x1
+PROFILE = 0x2
 
 EXPORTED = ("pcms_mls_opts_default", "pcms_grid_build", "pcms_grid_free", "pcms_neighbors",
-            "pcms_mls_transfer", "pcms_mls_transfer_grid", "pcms_version", "pcms_last_error")
+            "pcms_mls_transfer", "pcms_mls_transfer_grid", "pcms_last_phase_ms", "pcms_version",
+            "pcms_last_error")
 
 
 class PcmsError(RuntimeError):
@@ -80,6 +82,8 @@ def lib() -> ctypes.CDLL:
     L.pcms_mls_transfer_grid.argtypes = [P, P, i32, P, i64, i32, ctypes.POINTER(Radius), i32,
                                          ctypes.POINTER(MlsOpts), P, P, P]
     L.pcms_mls_transfer_grid.restype = i32
+    L.pcms_last_phase_ms.argtypes = [P, i32]
+    L.pcms_last_phase_ms.restype = i32
     L.pcms_version.argtypes = []
     L.pcms_version.restype = i32
     L.pcms_last_error.argtypes = []
@@ -90,6 +94,16 @@ def lib() -> ctypes.CDLL:
 
 def last_error() -> str:
     return lib().pcms_last_error().decode()
+
+
+PHASES = ("grid_build", "target_order", "field_gather", "search_fit")
+
+
+def last_phase_ms() -> dict:
+    """Phase times (ms) of this thread's last call made with the PROFILE flag."""
+    buf = (ctypes.c_float * 4)()
+    n = lib().pcms_last_phase_ms(ctypes.cast(buf, ctypes.c_void_p), 4)
+    return {PHASES[i]: float(buf[i]) for i in range(n)}
 
 
 def _check(code: int, allow=()):

@@ -23,9 +23,11 @@ from paper_2510_18838_amd import synth
 
 FP64, MIXED, MIXED_REFINE = 0, 1, 2
 TOL = {FP64: 1e-10, MIXED_REFINE: 1e-6, MIXED: 1e-4}
-# rounding of the normal equations grows with their conditioning: 1000 u64
-# for FP64 and refined mixed, 100 u32 for unrefined FP32 assembly
-COND = {FP64: 1e3 * 1.1e-16, MIXED_REFINE: 1e3 * 1.1e-16, MIXED: 100 * 6e-8}
+# rounding grows with the conditioning kappa of the moment matrix: 1000 u64
+# for FP64 normal equations; refined mixed solves exactly for FP32-rounded
+# per-neighbour data, whose effect is a small fraction of kappa u32; 100 u32
+# for unrefined FP32 assembly
+COND = {FP64: 1e3 * 1.1e-16, MIXED_REFINE: 1e-10, MIXED: 100 * 6e-8}
 CAPPED = 0x10
 
 
