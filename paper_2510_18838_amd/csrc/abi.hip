@@ -76,13 +76,15 @@ pcms_status check_opts(const pcms_mls_opts *o)
     return PCMS_OK;
 }
 
-// Cell sizing for a one-shot call: buckets about one support radius wide.
+// Cell sizing for a one-shot call: buckets a fixed fraction of the support
+// radius wide (0.7 of the expected kNN radius, one fixed or initial radius);
+// PCMS_CELL_FACTOR overrides the fraction.
 void cell_spec(const pcms_radius *r, int dim, double *cell_width, double *pts_per_cell)
 {
     *cell_width = 0.0;
     *pts_per_cell = 0.0;
     const char *env = getenv("PCMS_CELL_FACTOR");
-    double cf = env ? atof(env) : 1.0;
+    double cf = env ? atof(env) : (r->mode == PCMS_RADIUS_KNN ? 0.7 : 1.0);
     if (!(cf > 0.0)) cf = 1.0;
     if (r->mode == PCMS_RADIUS_KNN)
         *pts_per_cell = pow(cf, dim) * r->k / unit_ball_volume(dim);
@@ -105,6 +107,7 @@ void grid_alloc_free(Grid *g)
     if (g->params) (void)hipFree(g->params);
     if (g->cell_start) (void)hipFree(g->cell_start);
     if (g->perm) (void)hipFree(g->perm);
+    if (g->iperm) (void)hipFree(g->iperm);
     if (g->spts) (void)hipFree(g->spts);
     delete g;
 }
@@ -248,6 +251,7 @@ static pcms_status grid_create(int64_t n_src, int32_t dim, const double *inv_sca
         (e = hipMalloc(&g->params, sizeof(GridParams))) != hipSuccess ||
         (e = hipMalloc(&g->cell_start, sizeof(int) * ((size_t)g->n_cells_cap + 1))) != hipSuccess ||
         (e = hipMalloc(&g->perm, sizeof(int) * (size_t)n_src)) != hipSuccess ||
+        (e = hipMalloc(&g->iperm, sizeof(int) * (size_t)n_src)) != hipSuccess ||
         (e = hipMalloc(&g->spts, sizeof(double) * (size_t)n_src * dim)) != hipSuccess) {
         grid_alloc_free(g);
         return hip_fail(e, "hipMalloc(grid)");
@@ -399,12 +403,14 @@ pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, con
     sc.s = s;
     size_t o_cs = 256;
     size_t o_perm = o_cs + ((sizeof(int) * ((size_t)g.n_cells_cap + 1) + 255) & ~(size_t)255);
-    size_t o_spts = o_perm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
+    size_t o_iperm = o_perm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
+    size_t o_spts = o_iperm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
     size_t bytes = o_spts + sizeof(double) * (size_t)n_src * dim;
     if ((st = scratch_alloc(&sc.p, bytes, s)) != PCMS_OK) return st;
     g.params = (GridParams *)sc.p;
     g.cell_start = (int *)((char *)sc.p + o_cs);
     g.perm = (int *)((char *)sc.p + o_perm);
+    g.iperm = (int *)((char *)sc.p + o_iperm);
     g.spts = (double *)((char *)sc.p + o_spts);
     if ((st = build_grid_device(&g, src, cw, ppc, s)) != PCMS_OK) return st;
     return transfer_common(&g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts, s,

@@ -26,6 +26,8 @@ using std::pow;
 using std::sqrt;
 // Called by the emulation build when a lane addresses LDS words outside its own.
 [[noreturn]] void pcms_emu_lds_fault(int e, int words);
+// Work counters of the emulation build (rows walked, candidates tested, walks).
+extern long long pcms_emu_rows, pcms_emu_cands, pcms_emu_walks;
 #else
 #include <hip/hip_runtime.h>
 #define PCMS_HD __host__ __device__

@@ -191,8 +191,7 @@ PCMS_HD PCMS_INLINE int select_target(LaneSearch<D, UNIT> &S, const KArgs &a, in
         }
         if (n_found < a.n_min) st = PCMS_TGT_RADIUS_EXHAUSTED;
     } else {
-        double guess = S.knn_radius_guess(a.k) * 1.25;
-        r2 = S.kth(a.k, 0.0, 0, guess * guess, S.words / 2);
+        r2 = S.knn_r2(a.k);
         n_found = S.collect(r2);
     }
     n_kept = min(n_found, a.k_cap);

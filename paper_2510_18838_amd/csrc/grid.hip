@@ -43,24 +43,53 @@ __global__ void k_bbox_init(long long *bb, int dim)
     }
 }
 
-// Per-dimension min/max of the points; one atomic per wave per dimension.
-__global__ void k_bbox(const double *__restrict__ pts, int64_t n, int dim, long long *bb)
+// Per-dimension min/max of the points: wave reductions, then one atomic per
+// block and dimension.
+template <int D>
+__global__ void __launch_bounds__(256) k_bbox(const double *__restrict__ pts, int64_t n, long long *bb)
 {
-    for (int k = 0; k < dim; ++k) {
-        double mn = INFINITY, mx = -INFINITY;
-        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-             i += (int64_t)gridDim.x * blockDim.x) {
-            double x = pts[i * dim + k];
-            mn = fmin(mn, x);
-            mx = fmax(mx, x);
+    __shared__ double smn[4][D], smx[4][D];
+    double mn[D], mx[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        mn[k] = INFINITY;
+        mx[k] = -INFINITY;
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            double x = pts[i * D + k];
+            mn[k] = fmin(mn[k], x);
+            mx[k] = fmax(mx[k], x);
         }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
         for (int off = 32; off > 0; off >>= 1) {
-            mn = fmin(mn, __shfl_xor(mn, off));
-            mx = fmax(mx, __shfl_xor(mx, off));
+            mn[k] = fmin(mn[k], __shfl_xor(mn[k], off));
+            mx[k] = fmax(mx[k], __shfl_xor(mx[k], off));
         }
-        if ((threadIdx.x & 63) == 0 && mn <= mx) {
-            atomicMin(&bb[k], ordered_key(mn));
-            atomicMax(&bb[dim + k], ordered_key(mx));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            smn[w][k] = mn[k];
+            smx[w][k] = mx[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < D) {
+        const int k = threadIdx.x;
+        double a = smn[0][k], b = smx[0][k];
+        for (int v = 1; v < (int)(blockDim.x >> 6); ++v) {
+            a = fmin(a, smn[v][k]);
+            b = fmax(b, smx[v][k]);
+        }
+        if (a <= b) {
+            atomicMin(&bb[k], ordered_key(a));
+            atomicMax(&bb[D + k], ordered_key(b));
         }
     }
 }
@@ -78,15 +107,54 @@ __global__ void k_grid_params(const long long *bb, int dim, int64_t n, const dou
     grid_params_compute(lo, hi, dim, n, g, cell_width, pts_per_cell, cap, gp);
 }
 
+template <int D>
 __global__ void k_bucket_keys(const GridParams *__restrict__ gp, const double *__restrict__ pts,
                               int64_t n, unsigned *__restrict__ keys, int *__restrict__ vals)
 {
-    const GridParams p = *gp;
+    const GridParams &p = *gp;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        keys[i] = bucket_key(p, pts + i * p.dim);
+        int id = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) id += bucket_of(p, k, pts[i * D + k]) * p.stride[k];
+        keys[i] = (unsigned)id;
         vals[i] = (int)i;
     }
+}
+
+template <int D>
+void launch_bucket_keys(const GridParams *gp, const double *pts, int64_t n, unsigned *keys,
+                        int *vals, int blocks, hipStream_t s)
+{
+    k_bucket_keys<D><<<blocks, 256, 0, s>>>(gp, pts, n, keys, vals);
+}
+
+pcms_status bucket_keys(int dim, const GridParams *gp, const double *pts, int64_t n,
+                        unsigned *keys, int *vals, int blocks, hipStream_t s)
+{
+    switch (dim) {
+    case 1: launch_bucket_keys<1>(gp, pts, n, keys, vals, blocks, s); break;
+    case 2: launch_bucket_keys<2>(gp, pts, n, keys, vals, blocks, s); break;
+    case 3: launch_bucket_keys<3>(gp, pts, n, keys, vals, blocks, s); break;
+    case 4: launch_bucket_keys<4>(gp, pts, n, keys, vals, blocks, s); break;
+    default: launch_bucket_keys<5>(gp, pts, n, keys, vals, blocks, s); break;
+    }
+    PCMS_HIP(hipGetLastError());
+    return PCMS_OK;
+}
+
+pcms_status bbox(int dim, const double *pts, int64_t n, long long *bb, hipStream_t s)
+{
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    switch (dim) {
+    case 1: k_bbox<1><<<blocks, 256, 0, s>>>(pts, n, bb); break;
+    case 2: k_bbox<2><<<blocks, 256, 0, s>>>(pts, n, bb); break;
+    case 3: k_bbox<3><<<blocks, 256, 0, s>>>(pts, n, bb); break;
+    case 4: k_bbox<4><<<blocks, 256, 0, s>>>(pts, n, bb); break;
+    default: k_bbox<5><<<blocks, 256, 0, s>>>(pts, n, bb); break;
+    }
+    PCMS_HIP(hipGetLastError());
+    return PCMS_OK;
 }
 
 // --- stable LSD radix sort, 8-bit digits --------------------------------------
@@ -267,22 +335,25 @@ __global__ void k_cell_start(const GridParams *__restrict__ gp, const unsigned *
 }
 
 __global__ void k_gather_pts(const double *__restrict__ src, const int *__restrict__ perm,
-                             int64_t n, int dim, double *__restrict__ spts)
+                             int64_t n, int dim, double *__restrict__ spts, int *__restrict__ iperm)
 {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
         int64_t j = perm[p];
         for (int k = 0; k < dim; ++k) spts[p * dim + k] = src[j * dim + k];
+        iperm[j] = (int)p;
     }
 }
 
-__global__ void k_gather_vals(const double *__restrict__ vals, const int *__restrict__ perm,
-                              int64_t n, int nf, double *__restrict__ svals)
+// Fields into bucket order, [n][nf]: read each field coalesced in source
+// order, write the whole row of a source at its sorted slot.
+__global__ void k_scatter_vals(const double *__restrict__ vals, const int *__restrict__ iperm,
+                               int64_t n, int nf, double *__restrict__ svals)
 {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        int64_t j = perm[p];
-        for (int l = 0; l < nf; ++l) svals[p * nf + l] = vals[(int64_t)l * n + j];
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        double *row = svals + (int64_t)iperm[j] * nf;
+        for (int l = 0; l < nf; ++l) row[l] = vals[(int64_t)l * n + j];
     }
 }
 
@@ -329,19 +400,19 @@ pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
     PCMS_HIP(hipMemcpyAsync(gdev, grid->g, sizeof(double) * dim, hipMemcpyHostToDevice, s));
     k_bbox_init<<<1, 64, 0, s>>>(bb, dim);
     PCMS_HIP(hipGetLastError());
-    k_bbox<<<grid_blocks(n, 256), 256, 0, s>>>(src, n, dim, bb);
-    PCMS_HIP(hipGetLastError());
+    if ((st = bbox(dim, src, n, bb, s)) != PCMS_OK) return st;
     k_grid_params<<<1, 1, 0, s>>>(bb, dim, n, gdev, cell_width, pts_per_cell, grid->n_cells_cap,
                                   grid->params);
     PCMS_HIP(hipGetLastError());
-    k_bucket_keys<<<grid_blocks(n, 256), 256, 0, s>>>(grid->params, src, n, k0, grid->perm);
-    PCMS_HIP(hipGetLastError());
+    if ((st = bucket_keys(dim, grid->params, src, n, k0, grid->perm, grid_blocks(n, 256), s)) != PCMS_OK)
+        return st;
     st = radix_sort(k0, grid->perm, k1, v1, n, key_bits(grid->n_cells_cap), hist, scan_scratch, s);
     if (st != PCMS_OK) return st;
     k_cell_start<<<grid_blocks((int64_t)grid->n_cells_cap + 1, 256), 256, 0, s>>>(
         grid->params, k0, n, grid->cell_start);
     PCMS_HIP(hipGetLastError());
-    k_gather_pts<<<grid_blocks(n, 256), 256, 0, s>>>(src, grid->perm, n, dim, grid->spts);
+    k_gather_pts<<<grid_blocks(n, 256), 256, 0, s>>>(src, grid->perm, n, dim, grid->spts,
+                                                      grid->iperm);
     PCMS_HIP(hipGetLastError());
     scratch_free(raw, s);
     return PCMS_OK;
@@ -366,8 +437,8 @@ pcms_status sort_targets(const Grid *grid, const double *tgt, int64_t n_tgt, int
     int *hist = (int *)cur;
     cur += sizeof(int) * (size_t)256 * nb;
     int *scan_scratch = (int *)cur;
-    k_bucket_keys<<<grid_blocks(n, 256), 256, 0, s>>>(grid->params, tgt, n, k0, tperm);
-    PCMS_HIP(hipGetLastError());
+    if ((st = bucket_keys(grid->dim, grid->params, tgt, n, k0, tperm, grid_blocks(n, 256), s)) != PCMS_OK)
+        return st;
     st = radix_sort(k0, tperm, k1, v1, n, key_bits(grid->n_cells_cap), hist, scan_scratch, s);
     if (st != PCMS_OK) return st;
     scratch_free(raw, s);
@@ -377,8 +448,8 @@ pcms_status sort_targets(const Grid *grid, const double *tgt, int64_t n_tgt, int
 pcms_status gather_values(const Grid *grid, const double *vals, int n_fields, double *svals,
                           hipStream_t s)
 {
-    k_gather_vals<<<grid_blocks(grid->n_src, 256), 256, 0, s>>>(vals, grid->perm, grid->n_src,
-                                                               n_fields, svals);
+    k_scatter_vals<<<grid_blocks(grid->n_src, 256), 256, 0, s>>>(vals, grid->iperm, grid->n_src,
+                                                                n_fields, svals);
     PCMS_HIP(hipGetLastError());
     return PCMS_OK;
 }

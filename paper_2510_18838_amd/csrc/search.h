@@ -41,11 +41,14 @@ PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs,
                                      const double *__restrict__ spts, const double (&t)[D],
                                      double rho2, F &&f)
 {
+#ifdef PCMS_HOST_EMULATION
+    ++pcms_emu_walks;
+#endif
     const double rho = sqrt(rho2);
     int a[D], b[D], c[D];
 #pragma unroll
     for (int k = 1; k < D; ++k) {
-        double half = rho / gp.g[k] * (1.0 + 1e-9) + fabs(t[k]) * 1e-15 + 1e-300;
+        double half = (UNIT ? rho : rho / gp.g[k]) * (1.0 + 1e-9) + fabs(t[k]) * 1e-15 + 1e-300;
         a[k] = bucket_of(gp, k, t[k] - half);
         b[k] = bucket_of(gp, k, t[k] + half);
         c[k] = a[k];
@@ -63,21 +66,42 @@ PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs,
             // the first and last buckets also hold clamped coordinates
             if (c[k] == 0) blo = -INFINITY;
             if (c[k] == gp.n[k] - 1) bhi = INFINITY;
-            double dlt = fmax(fmax(blo - pad - t[k], t[k] - bhi - pad), 0.0) * gp.g[k];
+            double dlt = fmax(fmax(blo - pad - t[k], t[k] - bhi - pad), 0.0);
+            if (!UNIT) dlt *= gp.g[k];
             m2 = __builtin_fma(dlt, dlt, m2);
             row += c[k] * gp.stride[k];
         }
+#ifdef PCMS_HOST_EMULATION
+        ++pcms_emu_rows;
+#endif
         if (m2 <= rho2 * (1.0 + 1e-9)) {
             double rem2 = fmax(rho2 - m2 * (1.0 - 1e-9), 0.0);
-            double half0 = sqrt(rem2) / gp.g[0] * (1.0 + 1e-9) + fabs(t[0]) * 1e-15 + 1e-300;
+            double half0 = (UNIT ? sqrt(rem2) : sqrt(rem2) / gp.g[0]) * (1.0 + 1e-9) +
+                           fabs(t[0]) * 1e-15 + 1e-300;
             int a0 = bucket_of(gp, 0, t[0] - half0);
             int b0 = bucket_of(gp, 0, t[0] + half0);
-            int beg = cs[row + a0];
-            int end = cs[row + b0 + 1];
-            for (int p = beg; p < end; ++p) {
-                const double *s = spts + (size_t)p * D;
-                f(p, metric_d2<D, UNIT>(t, s, gp));
+            const int beg = cs[row + a0];
+            const int end = cs[row + b0 + 1];
+#ifdef PCMS_HOST_EMULATION
+            pcms_emu_cands += end - beg;
+#endif
+            // candidates of a row are contiguous: load kBatch points before
+            // testing them, so their loads are in flight together
+            constexpr int kBatch = 4;
+            int p = beg;
+            for (; p + kBatch <= end; p += kBatch) {
+                double sb[kBatch][D];
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q)
+#pragma unroll
+                    for (int k = 0; k < D; ++k) sb[q][k] = spts[(size_t)(p + q) * D + k];
+                double d2[kBatch];
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) d2[q] = metric_d2<D, UNIT>(t, sb[q], gp);
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) f(p + q, d2[q]);
             }
+            for (; p < end; ++p) f(p, metric_d2<D, UNIT>(t, spts + (size_t)p * D, gp));
         }
         int k = 1;
         while (k < D) {
@@ -286,24 +310,62 @@ struct LaneSearch {
                 each(h1, [&](int, double d2) {
                     if (d2 >= l1 && d2 < h1 && n < sb) dstore(n++, d2);
                 });
-                const int r = k - c_lo;   // 1-based rank inside [lo, hi)
-                double ans = h1;
-                for (int a = 0; a < n; ++a) {
-                    double v = dload(a);
-                    int less = 0, le = 0;
-                    for (int b2 = 0; b2 < n; ++b2) {
-                        double x = dload(b2);
-                        less += x < v;
-                        le += x <= v;
-                    }
-                    if (less < r && r <= le) ans = v;
-                }
-                return ans;
+                const double ans = buffer_rank(n, k - c_lo);   // rank inside [lo, hi)
+                return ans < INFINITY ? ans : h1;
             }
             // a single representable value left in [lo, hi): it is the answer
             if (!(nextafter(lo, INFINITY) < hi)) return lo;
         }
         return hi;
+    }
+
+    // r-th smallest (1-based) of the n doubles in the lane's LDS buffer.
+    PCMS_HD double buffer_rank(int n, int r)
+    {
+        double ans = INFINITY;
+        for (int a = 0; a < n; ++a) {
+            const double v = dload(a);
+            int less = 0, le = 0;
+            for (int b = 0; b < n; ++b) {
+                const double x = dload(b);
+                less += x < v;
+                le += x <= v;
+            }
+            if (less < r && r <= le) {
+                ans = v;
+                break;
+            }
+        }
+        return ans;
+    }
+
+    // Squared distance of the k-th nearest source.  One walk counts the
+    // sources below lo = (a g)^2 and buffers those in [lo, hi = (b g)^2), g
+    // the bucket-count estimate of the radius and [a, b] a window sized so
+    // that about a quarter of the buffer fills; when the k-th falls in the
+    // buffered interval it is ranked there, otherwise the general bracketing
+    // search continues from what the walk established.
+    PCMS_HD double knn_r2(int k)
+    {
+        const double g = knn_radius_guess(k);
+        const int cb = words / 2;
+        // half-width h of the window [1 - h, 1 + h] g: expected count
+        // k ((1 + h)^D - (1 - h)^D) ~ 2 D h k, sized to about 3/4 of the buffer
+        const double h = fmin(0.15, fmax(0.02, 0.75 * (double)cb / (2.0 * D * (double)k)));
+        const double lo = (1.0 - h) * (1.0 - h) * g * g, hi = (1.0 + h) * (1.0 + h) * g * g;
+        int c_lo = 0, n_in = 0;
+        each(hi, [&](int, double d2) {
+            if (d2 < lo) {
+                ++c_lo;
+            } else if (d2 < hi) {
+                if (n_in < cb) dstore(n_in, d2);
+                ++n_in;
+            }
+        });
+        if (c_lo < k && k <= c_lo + n_in && n_in <= cb) return buffer_rank(n_in, k - c_lo);
+        if (c_lo >= k) return kth(k, 0.0, 0, lo, cb);
+        if (c_lo + n_in < k) return kth(k, hi, c_lo + n_in, 4.0 * hi, cb);
+        return kth(k, lo, c_lo, hi, cb);
     }
 
     // Keeps the k_cap smallest (D, source index) among D < r2 in the list

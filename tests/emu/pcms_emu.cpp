@@ -14,6 +14,8 @@
 
 #include "fit.h"
 
+long long pcms_emu_rows = 0, pcms_emu_cands = 0, pcms_emu_walks = 0;
+
 [[noreturn]] void pcms_emu_lds_fault(int e, int words)
 {
     std::fprintf(stderr, "LDS word %d outside the lane's %d words\n", e, words);
@@ -291,6 +293,9 @@ int main(int argc, char **argv)
         default: die("bad dim");
     }
 #undef DIMCASE
+    std::fprintf(stderr, "work: walks %lld rows %lld candidates %lld per target: %.2f %.2f %.2f\n",
+                 pcms_emu_walks, pcms_emu_rows, pcms_emu_cands, (double)pcms_emu_walks / n_tgt,
+                 (double)pcms_emu_rows / n_tgt, (double)pcms_emu_cands / n_tgt);
     FILE *o = std::fopen(argv[2], "wb");
     if (!o) die("cannot open output");
     if (op == 0) {

@@ -36,10 +36,15 @@ def build(force=False) -> str:
 
 
 def _cell_spec(prob):
+    """Bucket sizing of a one-shot call (same rule as the library, including
+    its PCMS_CELL_FACTOR override)."""
+    env = os.environ.get("PCMS_CELL_FACTOR")
+    cf = float(env) if env else (0.7 if prob.mode == 1 else 1.0)
+    cf = cf if cf > 0 else 1.0
     if prob.mode == 1:
         d = prob.dim
-        return 0.0, prob.k / (math.pi ** (d / 2) / math.gamma(d / 2 + 1))
-    return prob.radius, 0.0
+        return 0.0, cf ** d * prob.k / (math.pi ** (d / 2) / math.gamma(d / 2 + 1))
+    return cf * prob.radius, 0.0
 
 
 def run(prob, op, precision=0, weight=0, lam=0.0, block=64, tgt=None):
@@ -70,6 +75,7 @@ def run(prob, op, precision=0, weight=0, lam=0.0, block=64, tgt=None):
         if res.returncode != 0:
             raise RuntimeError(f"emulation failed ({res.returncode}):\n{res.stderr[-4000:]}")
         raw = open(fout, "rb").read()
+        run.last_stderr = res.stderr
     off = 0
 
     def take(dtype, count):
