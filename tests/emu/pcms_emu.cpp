@@ -154,13 +154,30 @@ void run_xfer(const KArgs &a, const GridParams &gp, int block)
 {
     const int nblk = (a.n_tgt + block - 1) / block;
     std::vector<int> lds((size_t)block * a.words);
+    // per-wave divergence: sum over waves of the max per-lane walks / candidates
+    double wave_walks = 0, wave_cands = 0, lane_walks = 0, lane_cands = 0;
+    long long nw = 0;
     for (int b = 0; b < nblk; ++b) {
         std::fill(lds.begin(), lds.end(), 0x7f7f7f7f);
+        long long mw = 0, mc = 0;
         for (int lane = 0; lane < block; ++lane) {
             int i = b * block + lane;
+            long long w0 = pcms_emu_walks, c0 = pcms_emu_cands;
             if (i < a.n_tgt) xfer_target<D, P, MIXED, UNIT>(a, gp, i, lds.data(), lane, block);
+            mw = std::max(mw, pcms_emu_walks - w0);
+            mc = std::max(mc, pcms_emu_cands - c0);
+            if ((lane & 63) == 63 || i == a.n_tgt - 1) {
+                wave_walks += mw;
+                wave_cands += mc;
+                ++nw;
+                mw = mc = 0;
+            }
         }
     }
+    lane_walks = (double)pcms_emu_walks / a.n_tgt;
+    lane_cands = (double)pcms_emu_cands / a.n_tgt;
+    std::fprintf(stderr, "divergence: per wave max walks %.2f cands %.1f vs lane mean %.2f %.1f\n",
+                 wave_walks / nw, wave_cands / nw, lane_walks, lane_cands);
 }
 
 template <int D, bool UNIT>
