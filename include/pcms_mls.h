@@ -115,7 +115,7 @@ typedef struct {
     int32_t precision;        /* PCMS_FP64 / PCMS_MIXED / PCMS_MIXED_REFINE */
     double lambda;            /* Tikhonov parameter of Eq. 1, >= 0, in the radius-scaled basis */
     uint32_t flags;           /* PCMS_ASYNC | PCMS_PROFILE */
-    int32_t block;            /* targets per workgroup: 0 = library choice, else 64/128/256 */
+    int32_t block;            /* threads per workgroup (4 per target): 0 = library choice, else 64/128/256 */
     int32_t *summary;         /* device int32[4] or NULL: counts of statuses 1, 2, 3 and CAPPED */
 } pcms_mls_opts;
 

@@ -27,7 +27,17 @@ using std::sqrt;
 // Called by the emulation build when a lane addresses LDS words outside its own.
 [[noreturn]] void pcms_emu_lds_fault(int e, int words);
 // Work counters of the emulation build (rows walked, candidates tested, walks).
-extern long long pcms_emu_rows, pcms_emu_cands, pcms_emu_walks;
+extern thread_local long long pcms_emu_rows, pcms_emu_cands, pcms_emu_walks;
+// Collective operations of a lane group, provided by the emulation driver:
+// the G lanes of a group run as G threads meeting at a barrier per operation.
+struct EmuGroup;
+unsigned pcms_emu_ballot(EmuGroup *g, int q, bool p);
+double pcms_emu_sum(EmuGroup *g, int q, double x);
+float pcms_emu_sum(EmuGroup *g, int q, float x);
+int pcms_emu_sum(EmuGroup *g, int q, int x);
+double pcms_emu_min(EmuGroup *g, int q, double x);
+int pcms_emu_min(EmuGroup *g, int q, int x);
+void pcms_emu_sync(EmuGroup *g, int q);
 #else
 #include <hip/hip_runtime.h>
 #define PCMS_HD __host__ __device__
@@ -150,6 +160,63 @@ PCMS_HD PCMS_INLINE unsigned bucket_key(const GridParams &p, const double *x)
     for (int k = 0; k < p.dim; ++k) id += bucket_of(p, k, x[k]) * p.stride[k];
     return (unsigned)id;
 }
+
+// --- lane groups -----------------------------------------------------------
+// G consecutive lanes of a wave (G a power of two, <= 16) cooperate on one
+// target.  Group operations must be reached by all G lanes together (the
+// control flow around them is uniform within the group).
+template <int G>
+struct Grp {
+    int q;   // lane index inside the group
+#ifdef PCMS_HOST_EMULATION
+    EmuGroup *emu;
+    unsigned ballot(bool p) const { return pcms_emu_ballot(emu, q, p); }
+    template <class T>
+    T sum(T x) const { return pcms_emu_sum(emu, q, x); }
+    template <class T>
+    T min(T x) const { return pcms_emu_min(emu, q, x); }
+    void sync() const { pcms_emu_sync(emu, q); }
+#else
+    __device__ PCMS_INLINE unsigned ballot(bool p) const
+    {
+        const unsigned long long m = __ballot(p);
+        const int base = (int)(__lane_id() & ~(unsigned)(G - 1));
+        return (unsigned)(m >> base) & ((1u << G) - 1u);
+    }
+    // butterfly: every lane ends with the same value, summed in the same order
+    template <class T>
+    __device__ PCMS_INLINE T sum(T x) const
+    {
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) {
+            T y = __shfl_xor(x, off, 64);
+            x = (q & off) ? y + x : x + y;
+        }
+        return x;
+    }
+    template <class T>
+    __device__ PCMS_INLINE T min(T x) const
+    {
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) {
+            T y = __shfl_xor(x, off, 64);
+            x = y < x ? y : x;
+        }
+        return x;
+    }
+    // orders this lane's LDS accesses against the group's (one wavefront)
+    __device__ PCMS_INLINE void sync() const
+    {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+#endif
+    // lanes of mask m below this one
+    PCMS_HD PCMS_INLINE int below(unsigned m) const
+    {
+        return __builtin_popcount(m & ((1u << q) - 1u));
+    }
+};
 
 // --- pieces of the stable radix-sort scatter (one 8-bit digit per pass) ------
 // Lanes of one wave holding the same digit: AND of the per-bit ballots.

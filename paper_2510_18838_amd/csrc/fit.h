@@ -1,6 +1,8 @@
 // Per-target work of the neighbour-list and field-transfer kernels, written
-// as host+device functions of (arguments, target slot, LDS block, lane) so
-// the CPU emulation build runs exactly this code.
+// as host+device functions of (arguments, target slot, the target's LDS
+// words, lane group) so the CPU emulation build runs exactly this code.  The
+// G lanes of a target split the walks' candidates and the neighbours of the
+// fit passes; group sums combine their partial moments.
 //
 // Field transfer (PCMS paper, Section 3.2.1, Eq. 1): for target t with kept
 // sources s_e, weights w_e = phi(q_e), q_e = sqrt(D_e) / r, and monomials
@@ -152,7 +154,8 @@ struct KArgs {
     int max_iter;
     double r;
     int k_cap;
-    int words;             // LDS words per lane
+    int words;             // LDS words of a target's list/buffer (>= max(k_cap, 2))
+    int stride;            // LDS words between consecutive targets of a block (odd)
     int n_blocks;          // logical blocks (before XCD padding)
     // transfer only
     const double *svals;   // [n_src][nf], sorted order
@@ -171,9 +174,10 @@ struct KArgs {
 };
 
 // Radius and kept list for one target; returns the status bits, the count
-// inside the radius, the number of kept list entries and r^2.
-template <int D, bool UNIT>
-PCMS_HD PCMS_INLINE int select_target(LaneSearch<D, UNIT> &S, const KArgs &a, int &n_found,
+// inside the radius, the number of kept list entries and r^2 (all uniform
+// across the group).
+template <int D, bool UNIT, int G>
+PCMS_HD PCMS_INLINE int select_target(Search<D, UNIT, G> &S, const KArgs &a, int &n_found,
                                       int &n_kept, double &r2)
 {
     int st = PCMS_TGT_OK;
@@ -210,32 +214,31 @@ PCMS_HD PCMS_INLINE void load_point(const double *__restrict__ x, int i, double 
 }
 
 // Neighbour list of the target at sorted slot i (original indices, ascending).
-template <int D, bool UNIT>
-PCMS_HD PCMS_INLINE int nbr_target(const KArgs &a, const GridParams &gp, int i, int *lds, int lane,
-                                   int ls)
+template <int D, bool UNIT, int G>
+PCMS_HD PCMS_INLINE int nbr_target(const KArgs &a, const GridParams &gp, int i, int *L, Grp<G> g)
 {
     const int ti = a.tperm[i];
-    LaneSearch<D, UNIT> S{gp, a.cs, a.spts, a.perm, {}, lds, lane, ls, a.k_cap, a.words};
+    Search<D, UNIT, G> S{gp, a.cs, a.spts, a.perm, {}, L, a.k_cap, a.words, g};
     load_point<D>(a.tgt, ti, S.t);
     int n_found, n;
     double r2;
-    const int st = select_target<D, UNIT>(S, a, n_found, n, r2);
-    for (int e = 0; e < n; ++e) S.at(e) = a.perm[S.at(e)];
-    for (int e = 1; e < n; ++e) {
-        int x = S.at(e);
-        int j = e - 1;
-        while (j >= 0 && S.at(j) > x) {
-            S.at(j + 1) = S.at(j);
-            --j;
-        }
-        S.at(j + 1) = x;
-    }
+    const int st = select_target<D, UNIT, G>(S, a, n_found, n, r2);
+    for (int e = g.q; e < n; e += G) S.at(e) = a.perm[S.at(e)];
+    g.sync();
+    // source indices are distinct: each entry's rank is its output slot
     int32_t *row = a.nbr + (size_t)ti * a.k_cap;
-    for (int e = 0; e < n; ++e) row[e] = S.at(e);
-    a.n_kept[ti] = n;
-    if (a.n_found) a.n_found[ti] = n_found;
-    if (a.r2) a.r2[ti] = r2;
-    if (a.status) a.status[ti] = (uint8_t)st;
+    for (int e = g.q; e < n; e += G) {
+        const int v = S.at(e);
+        int rank = 0;
+        for (int x = 0; x < n; ++x) rank += S.at(x) < v;
+        row[rank] = v;
+    }
+    if (g.q == 0) {
+        a.n_kept[ti] = n;
+        if (a.n_found) a.n_found[ti] = n_found;
+        if (a.r2) a.r2[ti] = r2;
+        if (a.status) a.status[ti] = (uint8_t)st;
+    }
     return st;
 }
 
@@ -264,19 +267,18 @@ PCMS_HD PCMS_INLINE void neighbour_data(const GridParams &gp, const double (&t)[
 }
 
 // Field transfer of the target at sorted slot i; returns its status.
-template <int D, int P, bool MIXED, bool UNIT>
-PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i, int *lds,
-                                    int lane, int ls)
+template <int D, int P, bool MIXED, bool UNIT, int G>
+PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i, int *L, Grp<G> g)
 {
     constexpr int M = Basis<D, P>::M;
     constexpr int MM = Basis<D, P>::MM;
     using TA = typename std::conditional<MIXED, float, double>::type;   // assembly type
     const int ti = a.tperm[i];
-    LaneSearch<D, UNIT> S{gp, a.cs, a.spts, a.perm, {}, lds, lane, ls, a.k_cap, a.words};
+    Search<D, UNIT, G> S{gp, a.cs, a.spts, a.perm, {}, L, a.k_cap, a.words, g};
     load_point<D>(a.tgt, ti, S.t);
     int n_found, n;
     double r2;
-    int st = select_target<D, UNIT>(S, a, n_found, n, r2);
+    int st = select_target<D, UNIT, G>(S, a, n_found, n, r2);
     if ((st & 0xF) == PCMS_TGT_OK && n < M) st |= PCMS_TGT_UNDERDETERMINED;
     double y[M];
     double idg[M];
@@ -284,12 +286,13 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
     if ((st & 0xF) == PCMS_TGT_OK) {
         const double inv_h = 1.0 / sqrt(r2);
         const double inv_r2 = 1.0 / r2;
-        // moment matrix G = sum w p p^T (upper triangle)
+        // moment matrix G = sum w p p^T (upper triangle); lane q takes the
+        // neighbours e = q, q + G, ... and the group sums the partial moments
         {
-            TA G[MM];
+            TA Gm[MM];
 #pragma unroll
-            for (int j = 0; j < MM; ++j) G[j] = TA(0);
-            for (int e = 0; e < n; ++e) {
+            for (int j = 0; j < MM; ++j) Gm[j] = TA(0);
+            for (int e = g.q; e < n; e += G) {
                 TA p[M], w;
                 neighbour_data<D, P, UNIT, TA>(gp, S.t, a.spts + (size_t)S.at(e) * D, inv_h,
                                                inv_r2, a.weight, p, w);
@@ -298,11 +301,11 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                     TA wp = w * p[u];
 #pragma unroll
                     for (int v = u; v < M; ++v)
-                        G[tri<M>(u, v)] = __builtin_fma(wp, p[v], G[tri<M>(u, v)]);
+                        Gm[tri<M>(u, v)] = __builtin_fma(wp, p[v], Gm[tri<M>(u, v)]);
                 }
             }
 #pragma unroll
-            for (int j = 0; j < MM; ++j) R[j] = (double)G[j];
+            for (int j = 0; j < MM; ++j) R[j] = (double)g.sum(Gm[j]);
         }
 #pragma unroll
         for (int u = 0; u < M; ++u) R[tri<M>(u, u)] += a.lambda;
@@ -319,8 +322,8 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
             for (int step = 0; step < kMaxRefine; ++step) {
                 double res[M];
 #pragma unroll
-                for (int u = 0; u < M; ++u) res[u] = (u == 0 ? 1.0 : 0.0) - a.lambda * y[u];
-                for (int e = 0; e < n; ++e) {
+                for (int u = 0; u < M; ++u) res[u] = 0.0;
+                for (int e = g.q; e < n; e += G) {
                     TA p[M], w;
                     neighbour_data<D, P, UNIT, TA>(gp, S.t, a.spts + (size_t)S.at(e) * D, inv_h,
                                                    inv_r2, a.weight, p, w);
@@ -331,6 +334,9 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
 #pragma unroll
                     for (int u = 0; u < M; ++u) res[u] = __builtin_fma(c, (double)p[u], res[u]);
                 }
+#pragma unroll
+                for (int u = 0; u < M; ++u)
+                    res[u] = g.sum(res[u]) + ((u == 0 ? 1.0 : 0.0) - a.lambda * y[u]);
                 chol_solve<M>(R, idg, res);
                 double ny = 0.0, nd = 0.0;
 #pragma unroll
@@ -360,7 +366,7 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                 // centring leaves the fit unchanged only without regularisation
                 fref[l] = (MIXED && a.lambda == 0.0 && l0 + l < a.nf) ? sv0[l0 + l] : 0.0;
             }
-            for (int e = 0; e < n; ++e) {
+            for (int e = g.q; e < n; e += G) {
                 const int pe = S.at(e);
                 TA p[M], w;
                 neighbour_data<D, P, UNIT, TA>(gp, S.t, a.spts + (size_t)pe * D, inv_h, inv_r2,
@@ -375,13 +381,15 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                     if (l0 + l < a.nf) acc[l] = __builtin_fma(N, sv[l] - fref[l], acc[l]);
             }
 #pragma unroll
-            for (int l = 0; l < kFieldChunk; ++l)
-                if (l0 + l < a.nf) a.out[(size_t)(l0 + l) * a.n_tgt + ti] = acc[l] + fref[l];
+            for (int l = 0; l < kFieldChunk; ++l) {
+                const double v = g.sum(acc[l]) + fref[l];
+                if (l0 + l < a.nf && (l % G) == g.q) a.out[(size_t)(l0 + l) * a.n_tgt + ti] = v;
+            }
         }
     } else {
-        for (int l = 0; l < a.nf; ++l) a.out[(size_t)l * a.n_tgt + ti] = NAN;
+        for (int l = g.q; l < a.nf; l += G) a.out[(size_t)l * a.n_tgt + ti] = NAN;
     }
-    if (a.status) a.status[ti] = (uint8_t)st;
+    if (a.status && g.q == 0) a.status[ti] = (uint8_t)st;
     return st;
 }
 

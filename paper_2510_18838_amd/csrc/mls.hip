@@ -35,36 +35,44 @@ __device__ __forceinline__ void add_summary(int32_t *summary, int st, bool activ
     }
 }
 
-template <int D, bool UNIT>
+// G consecutive lanes per target; the block's targets are consecutive in
+// bucket order and each owns `stride` LDS words.
+constexpr int kGroup = 4;
+
+template <int D, bool UNIT, int G>
 __global__ void __launch_bounds__(256) k_neighbors(KArgs a)
 {
     extern __shared__ int lds[];
     const int lb = logical_block(a.n_blocks);
     if (lb >= a.n_blocks) return;
-    const int i = lb * blockDim.x + threadIdx.x;
-    const bool active = i < a.n_tgt;
+    const int slot = (int)threadIdx.x / G;
+    const int i = lb * ((int)blockDim.x / G) + slot;
+    const bool active = i < a.n_tgt;   // uniform within a group
+    const Grp<G> g{(int)(threadIdx.x & (G - 1))};
     int st = 0;
     if (active) {
         const GridParams gp = *a.gp;
-        st = nbr_target<D, UNIT>(a, gp, i, lds, (int)threadIdx.x, (int)blockDim.x);
+        st = nbr_target<D, UNIT, G>(a, gp, i, lds + slot * a.stride, g);
     }
-    add_summary(a.summary, st, active);
+    add_summary(a.summary, st, active && g.q == 0);
 }
 
-template <int D, int P, bool MIXED, bool UNIT>
+template <int D, int P, bool MIXED, bool UNIT, int G>
 __global__ void __launch_bounds__(256) k_transfer(KArgs a)
 {
     extern __shared__ int lds[];
     const int lb = logical_block(a.n_blocks);
     if (lb >= a.n_blocks) return;
-    const int i = lb * blockDim.x + threadIdx.x;
-    const bool active = i < a.n_tgt;
+    const int slot = (int)threadIdx.x / G;
+    const int i = lb * ((int)blockDim.x / G) + slot;
+    const bool active = i < a.n_tgt;   // uniform within a group
+    const Grp<G> g{(int)(threadIdx.x & (G - 1))};
     int st = 0;
     if (active) {
         const GridParams gp = *a.gp;
-        st = xfer_target<D, P, MIXED, UNIT>(a, gp, i, lds, (int)threadIdx.x, (int)blockDim.x);
+        st = xfer_target<D, P, MIXED, UNIT, G>(a, gp, i, lds + slot * a.stride, g);
     }
-    add_summary(a.summary, st, active);
+    add_summary(a.summary, st, active && g.q == 0);
 }
 
 __global__ void k_zero_ints(int32_t *p, int n)
@@ -78,13 +86,14 @@ using KernelFn = void (*)(KArgs);
 template <int D, bool UNIT>
 KernelFn pick_nbr()
 {
-    return k_neighbors<D, UNIT>;
+    return k_neighbors<D, UNIT, kGroup>;
 }
 
 template <int D, int P, bool UNIT>
 KernelFn pick_xfer(bool mixed)
 {
-    return mixed ? (KernelFn)k_transfer<D, P, true, UNIT> : (KernelFn)k_transfer<D, P, false, UNIT>;
+    return mixed ? (KernelFn)k_transfer<D, P, true, UNIT, kGroup>
+                 : (KernelFn)k_transfer<D, P, false, UNIT, kGroup>;
 }
 
 template <bool UNIT>
@@ -126,15 +135,18 @@ bool unit_metric(const Grid *g)
     return true;
 }
 
-// Per-lane LDS words: the kept list (k_cap entries), which also serves as a
-// buffer of k_cap / 2 doubles during the radius search (at least one).
+// LDS words of a target: the kept list (k_cap entries), which also serves as
+// a buffer of k_cap / 2 doubles during the radius search (at least one); the
+// per-target stride is odd so neighbouring targets start in different banks.
 int lane_words(int k_cap) { return k_cap < 2 ? 2 : k_cap; }
+int target_stride(int k_cap) { return lane_words(k_cap) | 1; }
 
+// Threads per block (kGroup lanes per target); the targets' LDS must fit
+// 64 KiB per workgroup.
 int pick_block(int requested, int k_cap)
 {
-    int b = requested > 0 ? requested : 64;
-    // the per-lane lists must fit 64 KiB of LDS per workgroup
-    while (b > 64 && (size_t)b * lane_words(k_cap) * sizeof(int) > 65536) b >>= 1;
+    int b = requested > 0 ? requested : 256;
+    while (b > 64 && (size_t)(b / kGroup) * target_stride(k_cap) * sizeof(int) > 65536) b >>= 1;
     return b;
 }
 
@@ -154,8 +166,10 @@ KArgs base_args(const LaunchSpec &ls, int block)
     a.max_iter = ls.radius.max_iter;
     a.r = ls.radius.r;
     a.k_cap = ls.k_cap;
-    a.n_blocks = (int)((ls.n_tgt + block - 1) / block);
+    const int tpb = block / kGroup;
+    a.n_blocks = (int)((ls.n_tgt + tpb - 1) / tpb);
     a.words = lane_words(ls.k_cap);
+    a.stride = target_stride(ls.k_cap);
     a.summary = ls.summary;
     return a;
 }
@@ -182,7 +196,7 @@ pcms_status launch_neighbors(const LaunchSpec &ls, int32_t *nbr, int32_t *n_kept
     a.status = status;
     KernelFn fn = unit_metric(ls.grid) ? nbr_table<true>(ls.grid->dim) : nbr_table<false>(ls.grid->dim);
     const int launch = ((a.n_blocks + 7) / 8) * 8;
-    const size_t shm = (size_t)block * lane_words(ls.k_cap) * sizeof(int);
+    const size_t shm = (size_t)(block / kGroup) * target_stride(ls.k_cap) * sizeof(int);
     hipLaunchKernelGGL(fn, dim3(launch), dim3(block), shm, s, a);
     PCMS_HIP(hipGetLastError());
     return PCMS_OK;
@@ -206,7 +220,7 @@ pcms_status launch_transfer(const LaunchSpec &ls, const double *svals, int n_fie
     KernelFn fn = unit_metric(ls.grid) ? xfer_table<true>(ls.grid->dim, degree, mixed)
                                        : xfer_table<false>(ls.grid->dim, degree, mixed);
     const int launch = ((a.n_blocks + 7) / 8) * 8;
-    const size_t shm = (size_t)block * lane_words(ls.k_cap) * sizeof(int);
+    const size_t shm = (size_t)(block / kGroup) * target_stride(ls.k_cap) * sizeof(int);
     hipLaunchKernelGGL(fn, dim3(launch), dim3(block), shm, s, a);
     PCMS_HIP(hipGetLastError());
     return PCMS_OK;

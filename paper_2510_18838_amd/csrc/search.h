@@ -1,4 +1,4 @@
-// Per-target neighbour search on the uniform grid, one lane per target.
+// Per-target neighbour search on the uniform grid, G lanes per target.
 //
 // Selection follows the PCMS paper, Section 3.2.1: the source set of target
 // t is { s_j : phi(s_j, t) > 0 }, i.e. the sources strictly inside the
@@ -14,6 +14,10 @@
 // row (c_1..c_{d-1}) the buckets c_0 in [a, b] form one contiguous range of
 // sorted sources.  Rows whose slab is farther than the radius are skipped and
 // each row's c_0 range is narrowed to the chord of the ball in that slab.
+// The G lanes of a target walk the same rows (uniform control flow) and take
+// the candidates of a row in an interleaved order, so their loads are
+// contiguous; candidates reach the per-step callback in ascending sorted
+// order, which the ordered ballot compaction of the lists preserves.
 #pragma once
 
 #include "device_common.h"
@@ -22,7 +26,7 @@ namespace pcms {
 
 template <int D, bool UNIT>
 PCMS_HD PCMS_INLINE double metric_d2(const double (&t)[D], const double *__restrict__ s,
-                                            const GridParams &p)
+                                     const GridParams &p)
 {
     double u = UNIT ? (t[0] - s[0]) : (t[0] - s[0]) * p.g[0];
     double acc = u * u;
@@ -34,15 +38,18 @@ PCMS_HD PCMS_INLINE double metric_d2(const double (&t)[D], const double *__restr
     return acc;
 }
 
-// Calls f(p, D) for every sorted source p in the buckets that can hold a
-// source with D < rho2 (a superset of the ball).  rho2 may be +inf.
-template <int D, bool UNIT, class F>
+// Calls f(p, D, valid) for every sorted source p in the buckets that can hold
+// a source with D < rho2 (a superset of the ball), kBatch * G candidates per
+// step; every lane of the group calls f the same number of times, with valid
+// = false on the padding slots past a row's end.  rho2 may be +inf.
+template <int D, bool UNIT, int G, class F>
 PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs,
-                                     const double *__restrict__ spts, const double (&t)[D],
-                                     double rho2, F &&f)
+                              const double *__restrict__ spts, const double (&t)[D], double rho2,
+                              int q, F &&f)
 {
+    constexpr int kBatch = 4;
 #ifdef PCMS_HOST_EMULATION
-    ++pcms_emu_walks;
+    if (q == 0) ++pcms_emu_walks;
 #endif
     const double rho = sqrt(rho2);
     int a[D], b[D], c[D];
@@ -72,7 +79,7 @@ PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs,
             row += c[k] * gp.stride[k];
         }
 #ifdef PCMS_HOST_EMULATION
-        ++pcms_emu_rows;
+        if (q == 0) ++pcms_emu_rows;
 #endif
         if (m2 <= rho2 * (1.0 + 1e-9)) {
             double rem2 = fmax(rho2 - m2 * (1.0 - 1e-9), 0.0);
@@ -83,25 +90,25 @@ PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs,
             const int beg = cs[row + a0];
             const int end = cs[row + b0 + 1];
 #ifdef PCMS_HOST_EMULATION
-            pcms_emu_cands += end - beg;
+            if (q == 0) pcms_emu_cands += end - beg;
 #endif
-            // candidates of a row are contiguous: load kBatch points before
-            // testing them, so their loads are in flight together
-            constexpr int kBatch = 4;
-            int p = beg;
-            for (; p + kBatch <= end; p += kBatch) {
+            for (int p0 = beg; p0 < end; p0 += kBatch * G) {
+                // slot j of lane q is candidate p0 + j*G + q: the group's
+                // loads of one slot are contiguous
                 double sb[kBatch][D];
+                int pp[kBatch];
+                bool ok[kBatch];
 #pragma unroll
-                for (int q = 0; q < kBatch; ++q)
+                for (int j = 0; j < kBatch; ++j) {
+                    pp[j] = p0 + j * G + q;
+                    ok[j] = pp[j] < end;
+                    const int pl = ok[j] ? pp[j] : beg;
 #pragma unroll
-                    for (int k = 0; k < D; ++k) sb[q][k] = spts[(size_t)(p + q) * D + k];
-                double d2[kBatch];
+                    for (int k = 0; k < D; ++k) sb[j][k] = spts[(size_t)pl * D + k];
+                }
 #pragma unroll
-                for (int q = 0; q < kBatch; ++q) d2[q] = metric_d2<D, UNIT>(t, sb[q], gp);
-#pragma unroll
-                for (int q = 0; q < kBatch; ++q) f(p + q, d2[q]);
+                for (int j = 0; j < kBatch; ++j) f(pp[j], metric_d2<D, UNIT>(t, sb[j], gp), ok[j]);
             }
-            for (; p < end; ++p) f(p, metric_d2<D, UNIT>(t, spts + (size_t)p * D, gp));
         }
         int k = 1;
         while (k < D) {
@@ -116,35 +123,33 @@ PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs,
     }
 }
 
-// Per-lane search state.  The lane's `words` LDS words are interleaved by
-// lane: word e of this lane is base[e * ls + lane].  They hold the kept list
-// (k_cap entries) and, during the radius search, a buffer of words / 2
-// doubles, double j split over this lane's words 2j (low half) and 2j + 1.
-template <int D, bool UNIT>
-struct LaneSearch {
+// Search state of one target, shared by its G lanes.  The target's `words`
+// LDS words L[0..words) hold the kept list (k_cap entries) and, during the
+// radius search, a buffer of words / 2 doubles (double j in words 2j, 2j+1).
+template <int D, bool UNIT, int G>
+struct Search {
     const GridParams &gp;
     const int *__restrict__ cs;
     const double *__restrict__ spts;
     const int *__restrict__ perm;
     double t[D];
-    int *base;  // block LDS base
-    int lane;   // lane index inside the block
-    int ls;     // lanes per block
+    int *L;     // this target's LDS words
     int k_cap;
-    int words;  // LDS words per lane (>= max(k_cap, 2))
+    int words;  // >= max(k_cap, 2)
+    Grp<G> g;
 
     PCMS_HD PCMS_INLINE int &at(int e)
     {
 #ifdef PCMS_HOST_EMULATION
         if (e < 0 || e >= words) pcms_emu_lds_fault(e, words);
 #endif
-        return base[e * ls + lane];
+        return L[e];
     }
     PCMS_HD PCMS_INLINE void dstore(int j, double v)
     {
-        unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-        at(2 * j) = (int)(unsigned)(b & 0xffffffffull);
-        at(2 * j + 1) = (int)(unsigned)(b >> 32);
+        unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
+        at(2 * j) = (int)(unsigned)(bits & 0xffffffffull);
+        at(2 * j + 1) = (int)(unsigned)(bits >> 32);
     }
     PCMS_HD PCMS_INLINE double dload(int j)
     {
@@ -156,7 +161,7 @@ struct LaneSearch {
     template <class F>
     PCMS_HD PCMS_INLINE void each(double rho2, F &&f)
     {
-        walk<D, UNIT>(gp, cs, spts, t, rho2, f);
+        walk<D, UNIT, G>(gp, cs, spts, t, rho2, g.q, f);
     }
 
     // Squared metric distance from t to the farthest corner of the bucket
@@ -173,16 +178,21 @@ struct LaneSearch {
         return acc * (1.0 + 1e-6) + 1e-300;
     }
 
-    // Collects every source with D < r2 into the list (up to k_cap); returns the count.
+    // Collects every source with D < r2 into the list (up to k_cap, in walk
+    // order); returns the count (the same on every lane of the group).
     PCMS_HD int collect(double r2)
     {
         int n = 0;
-        each(r2, [&](int p, double d2) {
-            if (d2 < r2) {
-                if (n < k_cap) at(n) = p;
-                ++n;
+        each(r2, [&](int p, double d2, bool ok) {
+            const bool acc = ok && d2 < r2;
+            const unsigned m = g.ballot(acc);
+            if (acc) {
+                const int pos = n + g.below(m);
+                if (pos < k_cap) at(pos) = p;
             }
+            n += __builtin_popcount(m);
         });
+        g.sync();
         return n;
     }
 
@@ -229,12 +239,76 @@ struct LaneSearch {
         return pow((double)k * vol / ((double)count * vball), 1.0 / D);
     }
 
+    // Appends the values D in [lo, hi) to the buffer (ordered compaction,
+    // at most cb kept); returns (group-uniform) the counts below lo and in
+    // [lo, hi).
+    PCMS_HD void buffer_bracket(double lo, double hi, int cb, int &c_lo, int &n_in)
+    {
+        int below = 0, n = 0;
+        each(hi, [&](int, double d2, bool ok) {
+            below += ok && d2 < lo;
+            const bool in = ok && d2 >= lo && d2 < hi;
+            const unsigned m = g.ballot(in);
+            if (in) {
+                const int pos = n + g.below(m);
+                if (pos < cb) dstore(pos, d2);
+            }
+            n += __builtin_popcount(m);
+        });
+        g.sync();
+        c_lo = g.sum(below);
+        n_in = n;
+    }
+
+    // r-th smallest (1-based) of the n doubles in the buffer; the lanes rank
+    // interleaved entries and the group takes the minimum found.
+    PCMS_HD double buffer_rank(int n, int r)
+    {
+        double ans = INFINITY;
+        for (int a0 = 0; a0 < n; a0 += G) {
+            const int a = a0 + g.q;
+            if (a < n) {
+                const double v = dload(a);
+                int less = 0, le = 0;
+                for (int b = 0; b < n; ++b) {
+                    const double x = dload(b);
+                    less += x < v;
+                    le += x <= v;
+                }
+                if (less < r && r <= le) ans = v;
+            }
+        }
+        return g.min(ans);
+    }
+
+    // Squared distance of the k-th nearest source.  One walk counts the
+    // sources below lo = ((1 - h) g)^2 and buffers those in
+    // [lo, hi = ((1 + h) g)^2), g the bucket-count estimate of the radius;
+    // when the k-th falls in the buffered interval it is ranked there,
+    // otherwise the general bracketing search continues from what the walk
+    // established.
+    PCMS_HD double knn_r2(int k)
+    {
+        const double gr = knn_radius_guess(k);
+        const int cb = words / 2;
+        // expected count in the window k ((1 + h)^D - (1 - h)^D) ~ 2 D h k,
+        // sized to about 3/4 of the buffer
+        const double h = fmin(0.15, fmax(0.02, 0.75 * (double)cb / (2.0 * D * (double)k)));
+        const double lo = (1.0 - h) * (1.0 - h) * gr * gr, hi = (1.0 + h) * (1.0 + h) * gr * gr;
+        int c_lo, n_in;
+        buffer_bracket(lo, hi, cb, c_lo, n_in);
+        if (c_lo < k && k <= c_lo + n_in && n_in <= cb) return buffer_rank(n_in, k - c_lo);
+        if (c_lo >= k) return kth(k, 0.0, 0, lo, cb);
+        if (c_lo + n_in < k) return kth(k, hi, c_lo + n_in, 4.0 * hi, cb);
+        return kth(k, lo, c_lo, hi, cb);
+    }
+
     // Exact k-th smallest D (1-based) over all sources, given a bracket:
     // #(D < lo) = c_lo < k, and hi a first guess for an upper bound (grown
     // when #(D < hi) < k).  Each round counts the sources of [lo, hi) into 8
     // sub-intervals with one walk; once the interval holding the k-th has at
-    // most `sb` (<= words / 2) sources they are copied into the lane's LDS
-    // buffer and ranked.
+    // most `sb` (<= words / 2) sources they are copied into the buffer and
+    // ranked.
     PCMS_HD double kth(int k, double lo, int c_lo, double hi, int sb)
     {
         constexpr int NB = 8;
@@ -244,11 +318,13 @@ struct LaneSearch {
             const bool from_zero = (lo == 0.0);
 #pragma unroll
             for (int j = 0; j < NB - 1; ++j) {
-                // from zero: equal expected counts, (j+1)/NB of the volume;
-                // otherwise linear in D
-                double f = from_zero ? pow((double)(j + 1) / NB, 2.0 / D) : (double)(j + 1) / NB;
-                double sj = lo + (hi - lo) * f;
-                sp[j] = fmin(fmax(sj, lo), hi);
+                // from zero: equal expected counts, ((j + 1) / NB)^(2 / D) of
+                // the interval; otherwise linear in D
+                const double x = (double)(j + 1) / NB;
+                const double f0 = D == 1 ? x * x : D == 2 ? x : D == 3 ? cbrt(x * x)
+                                : D == 4 ? sqrt(x) : pow(x, 0.4);
+                const double f = from_zero ? f0 : x;
+                sp[j] = fmin(fmax(lo + (hi - lo) * f, lo), hi);
             }
             sp[NB - 1] = hi;
             int cnt[NB];
@@ -257,8 +333,8 @@ struct LaneSearch {
             const double l0 = lo, h0 = hi;
             double vmin = h0;   // smallest D in [lo, hi) and its multiplicity
             int neq = 0;
-            each(h0, [&](int, double d2) {
-                if (d2 >= l0 && d2 < h0) {
+            each(h0, [&](int, double d2, bool ok) {
+                if (ok && d2 >= l0 && d2 < h0) {
 #pragma unroll
                     for (int j = 0; j < NB; ++j) cnt[j] += d2 < sp[j];
                     if (d2 < vmin) {
@@ -268,6 +344,13 @@ struct LaneSearch {
                     neq += d2 == vmin;
                 }
             });
+#pragma unroll
+            for (int j = 0; j < NB; ++j) cnt[j] = g.sum(cnt[j]);
+            {
+                const double gmin = g.min(vmin);
+                neq = g.sum(vmin == gmin ? neq : 0);
+                vmin = gmin;
+            }
             if (c_lo + cnt[NB - 1] < k) {     // the k-th lies at or above hi
                 // every source has D < farr, so the count reaches k there
                 // (k <= n_src); nothing above it is left to search
@@ -305,67 +388,15 @@ struct LaneSearch {
                 nin -= neq;
             }
             if (nin <= sb) {
-                int n = 0;
-                const double l1 = lo, h1 = hi;
-                each(h1, [&](int, double d2) {
-                    if (d2 >= l1 && d2 < h1 && n < sb) dstore(n++, d2);
-                });
-                const double ans = buffer_rank(n, k - c_lo);   // rank inside [lo, hi)
-                return ans < INFINITY ? ans : h1;
+                int cl, n;
+                buffer_bracket(lo, hi, sb, cl, n);
+                const double ans = buffer_rank(min(n, sb), k - c_lo);
+                return ans < INFINITY ? ans : hi;
             }
             // a single representable value left in [lo, hi): it is the answer
             if (!(nextafter(lo, INFINITY) < hi)) return lo;
         }
         return hi;
-    }
-
-    // r-th smallest (1-based) of the n doubles in the lane's LDS buffer.
-    PCMS_HD double buffer_rank(int n, int r)
-    {
-        double ans = INFINITY;
-        for (int a = 0; a < n; ++a) {
-            const double v = dload(a);
-            int less = 0, le = 0;
-            for (int b = 0; b < n; ++b) {
-                const double x = dload(b);
-                less += x < v;
-                le += x <= v;
-            }
-            if (less < r && r <= le) {
-                ans = v;
-                break;
-            }
-        }
-        return ans;
-    }
-
-    // Squared distance of the k-th nearest source.  One walk counts the
-    // sources below lo = (a g)^2 and buffers those in [lo, hi = (b g)^2), g
-    // the bucket-count estimate of the radius and [a, b] a window sized so
-    // that about a quarter of the buffer fills; when the k-th falls in the
-    // buffered interval it is ranked there, otherwise the general bracketing
-    // search continues from what the walk established.
-    PCMS_HD double knn_r2(int k)
-    {
-        const double g = knn_radius_guess(k);
-        const int cb = words / 2;
-        // half-width h of the window [1 - h, 1 + h] g: expected count
-        // k ((1 + h)^D - (1 - h)^D) ~ 2 D h k, sized to about 3/4 of the buffer
-        const double h = fmin(0.15, fmax(0.02, 0.75 * (double)cb / (2.0 * D * (double)k)));
-        const double lo = (1.0 - h) * (1.0 - h) * g * g, hi = (1.0 + h) * (1.0 + h) * g * g;
-        int c_lo = 0, n_in = 0;
-        each(hi, [&](int, double d2) {
-            if (d2 < lo) {
-                ++c_lo;
-            } else if (d2 < hi) {
-                if (n_in < cb) dstore(n_in, d2);
-                ++n_in;
-            }
-        });
-        if (c_lo < k && k <= c_lo + n_in && n_in <= cb) return buffer_rank(n_in, k - c_lo);
-        if (c_lo >= k) return kth(k, 0.0, 0, lo, cb);
-        if (c_lo + n_in < k) return kth(k, hi, c_lo + n_in, 4.0 * hi, cb);
-        return kth(k, lo, c_lo, hi, cb);
     }
 
     // Keeps the k_cap smallest (D, source index) among D < r2 in the list
@@ -376,14 +407,18 @@ struct LaneSearch {
         const double v = kth(k_cap, 0.0, 0, r2, words / 2);
         const double vnext = nextafter(v, INFINITY);
         int n = 0, c_eq = 0;
-        each(vnext, [&](int p, double d2) {
-            if (d2 < v) {
-                if (n < k_cap) at(n) = p;
-                ++n;
-            } else if (d2 == v) {
-                ++c_eq;
+        each(vnext, [&](int p, double d2, bool ok) {
+            const bool acc = ok && d2 < v;
+            const unsigned m = g.ballot(acc);
+            if (acc) {
+                const int pos = n + g.below(m);
+                if (pos < k_cap) at(pos) = p;
             }
+            n += __builtin_popcount(m);
+            c_eq += ok && d2 == v;
         });
+        g.sync();
+        c_eq = g.sum(c_eq);
         const int need = k_cap - n;
         if (need <= 0) return k_cap;
         int jthr = 0x7fffffff;
@@ -391,20 +426,27 @@ struct LaneSearch {
             int prev = -1;
             for (int r = 0; r < need; ++r) {
                 int best = 0x7fffffff;
-                each(vnext, [&](int p, double d2) {
-                    if (d2 == v) {
-                        int j = perm[p];
+                each(vnext, [&](int p, double d2, bool ok) {
+                    if (ok && d2 == v) {
+                        const int j = perm[p];
                         if (j > prev && j < best) best = j;
                     }
                 });
-                prev = best;
+                prev = g.min(best);
             }
             jthr = prev;
         }
-        each(vnext, [&](int p, double d2) {
-            if (d2 == v && perm[p] <= jthr && n < k_cap) at(n++) = p;
+        each(vnext, [&](int p, double d2, bool ok) {
+            const bool acc = ok && d2 == v && perm[p] <= jthr;
+            const unsigned m = g.ballot(acc);
+            if (acc) {
+                const int pos = n + g.below(m);
+                if (pos < k_cap) at(pos) = p;
+            }
+            n += __builtin_popcount(m);
         });
-        return n;
+        g.sync();
+        return min(n, k_cap);
     }
 };
 

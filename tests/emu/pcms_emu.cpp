@@ -6,15 +6,93 @@
 // Every LDS word access is bounds-checked per lane.
 //
 // Usage: pcms_emu <input.bin> <output.bin>   (format written by emu_driver.py)
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "fit.h"
 
-long long pcms_emu_rows = 0, pcms_emu_cands = 0, pcms_emu_walks = 0;
+thread_local long long pcms_emu_rows = 0, pcms_emu_cands = 0, pcms_emu_walks = 0;
+
+// Spinning barrier for the few threads of one lane group.
+struct SpinBarrier {
+    int n;
+    std::atomic<int> count{0};
+    std::atomic<unsigned> gen{0};
+    explicit SpinBarrier(int n_) : n(n_) {}
+    void arrive_and_wait()
+    {
+        const unsigned g0 = gen.load(std::memory_order_acquire);
+        if (count.fetch_add(1, std::memory_order_acq_rel) + 1 == n) {
+            count.store(0, std::memory_order_relaxed);
+            gen.fetch_add(1, std::memory_order_acq_rel);
+        } else {
+            int spins = 0;
+            while (gen.load(std::memory_order_acquire) == g0)
+                if (++spins > 4096) std::this_thread::yield();
+        }
+    }
+};
+
+// The G lanes of a group run as G threads; every collective operation is a
+// barrier round in which each lane publishes its value, then all read.
+struct EmuGroup {
+    int G;
+    SpinBarrier bar;
+    double d[16];
+    float f[16];
+    int i[16];
+    bool b[16];
+    explicit EmuGroup(int g) : G(g), bar(g) {}
+};
+
+unsigned pcms_emu_ballot(EmuGroup *g, int q, bool p)
+{
+    g->b[q] = p;
+    g->bar.arrive_and_wait();
+    unsigned m = 0;
+    for (int x = 0; x < g->G; ++x) m |= (unsigned)g->b[x] << x;
+    g->bar.arrive_and_wait();
+    return m;
+}
+
+// the same butterfly as the kernels' xor shuffles, lower lane's value first
+template <class T>
+static T butterfly(EmuGroup *g, int q, T x, T *slot, bool is_min)
+{
+    slot[q] = x;
+    g->bar.arrive_and_wait();
+    T v[16];
+    for (int k = 0; k < g->G; ++k) v[k] = slot[k];
+    for (int off = g->G / 2; off > 0; off >>= 1) {
+        T nv[16];
+        for (int k = 0; k < g->G; ++k) {
+            T mine = v[k], other = v[k ^ off];
+            if (is_min) nv[k] = other < mine ? other : mine;
+            else nv[k] = (k & off) ? other + mine : mine + other;
+        }
+        for (int k = 0; k < g->G; ++k) v[k] = nv[k];
+    }
+    g->bar.arrive_and_wait();
+    return v[q];
+}
+
+double pcms_emu_sum(EmuGroup *g, int q, double x) { return butterfly(g, q, x, g->d, false); }
+float pcms_emu_sum(EmuGroup *g, int q, float x) { return butterfly(g, q, x, g->f, false); }
+int pcms_emu_sum(EmuGroup *g, int q, int x) { return butterfly(g, q, x, g->i, false); }
+double pcms_emu_min(EmuGroup *g, int q, double x) { return butterfly(g, q, x, g->d, true); }
+int pcms_emu_min(EmuGroup *g, int q, int x) { return butterfly(g, q, x, g->i, true); }
+void pcms_emu_sync(EmuGroup *g, int q)
+{
+    (void)q;
+    g->bar.arrive_and_wait();
+}
+
+long long g_rows = 0, g_cands = 0, g_walks = 0;
 
 [[noreturn]] void pcms_emu_lds_fault(int e, int words)
 {
@@ -135,49 +213,67 @@ int key_bits(int cap)
     return b;
 }
 
-template <int D, bool UNIT>
-void run_nbr(const KArgs &a, const GridParams &gp, int block)
+constexpr int kGroup = 4;   // lanes per target, as in the kernels
+
+// Runs body(i, L, grp) for every target on kGroup threads (lane q = thread q),
+// each target with its own poisoned LDS words; reports work per wave.
+template <class Body>
+void run_groups(const KArgs &a, Body body)
 {
-    const int nblk = (a.n_tgt + block - 1) / block;
-    std::vector<int> lds((size_t)block * a.words);
-    for (int b = 0; b < nblk; ++b) {
-        std::fill(lds.begin(), lds.end(), 0x7f7f7f7f);
-        for (int lane = 0; lane < block; ++lane) {
-            int i = b * block + lane;
-            if (i < a.n_tgt) nbr_target<D, UNIT>(a, gp, i, lds.data(), lane, block);
-        }
+    std::vector<int> lds((size_t)std::max(a.n_tgt, 1) * a.words, 0x7f7f7f7f);
+    EmuGroup ctx(kGroup);
+    std::vector<long long> walks(a.n_tgt), cands(a.n_tgt);
+    std::vector<std::thread> th;
+    for (int q = 0; q < kGroup; ++q) {
+        th.emplace_back([&, q]() {
+            for (int i = 0; i < a.n_tgt; ++i) {
+                const long long w0 = pcms_emu_walks, c0 = pcms_emu_cands;
+                body(i, lds.data() + (size_t)i * a.words, Grp<kGroup>{q, &ctx});
+                if (q == 0) {
+                    walks[i] = pcms_emu_walks - w0;
+                    cands[i] = pcms_emu_cands - c0;
+                }
+                ctx.bar.arrive_and_wait();
+            }
+            if (q == 0) {
+                g_rows = pcms_emu_rows;
+                g_cands = pcms_emu_cands;
+                g_walks = pcms_emu_walks;
+            }
+        });
     }
+    for (auto &t : th) t.join();
+    // divergence: a wave holds 64 / kGroup consecutive targets
+    const int tw = 64 / kGroup;
+    double mw = 0, mc = 0;
+    long long nw = 0;
+    for (int i0 = 0; i0 < a.n_tgt; i0 += tw) {
+        long long w = 0, c = 0;
+        for (int i = i0; i < std::min(a.n_tgt, i0 + tw); ++i) {
+            w = std::max(w, walks[i]);
+            c = std::max(c, cands[i]);
+        }
+        mw += w;
+        mc += c;
+        ++nw;
+    }
+    if (nw)
+        std::fprintf(stderr, "divergence: per wave max walks %.2f cands %.1f vs target mean %.2f %.1f\n",
+                     mw / nw, mc / nw, (double)g_walks / a.n_tgt, (double)g_cands / a.n_tgt);
+}
+
+template <int D, bool UNIT>
+void run_nbr(const KArgs &a, const GridParams &gp, int)
+{
+    run_groups(a, [&](int i, int *L, Grp<kGroup> g) { nbr_target<D, UNIT, kGroup>(a, gp, i, L, g); });
 }
 
 template <int D, int P, bool MIXED, bool UNIT>
-void run_xfer(const KArgs &a, const GridParams &gp, int block)
+void run_xfer(const KArgs &a, const GridParams &gp, int)
 {
-    const int nblk = (a.n_tgt + block - 1) / block;
-    std::vector<int> lds((size_t)block * a.words);
-    // per-wave divergence: sum over waves of the max per-lane walks / candidates
-    double wave_walks = 0, wave_cands = 0, lane_walks = 0, lane_cands = 0;
-    long long nw = 0;
-    for (int b = 0; b < nblk; ++b) {
-        std::fill(lds.begin(), lds.end(), 0x7f7f7f7f);
-        long long mw = 0, mc = 0;
-        for (int lane = 0; lane < block; ++lane) {
-            int i = b * block + lane;
-            long long w0 = pcms_emu_walks, c0 = pcms_emu_cands;
-            if (i < a.n_tgt) xfer_target<D, P, MIXED, UNIT>(a, gp, i, lds.data(), lane, block);
-            mw = std::max(mw, pcms_emu_walks - w0);
-            mc = std::max(mc, pcms_emu_cands - c0);
-            if ((lane & 63) == 63 || i == a.n_tgt - 1) {
-                wave_walks += mw;
-                wave_cands += mc;
-                ++nw;
-                mw = mc = 0;
-            }
-        }
-    }
-    lane_walks = (double)pcms_emu_walks / a.n_tgt;
-    lane_cands = (double)pcms_emu_cands / a.n_tgt;
-    std::fprintf(stderr, "divergence: per wave max walks %.2f cands %.1f vs lane mean %.2f %.1f\n",
-                 wave_walks / nw, wave_cands / nw, lane_walks, lane_cands);
+    run_groups(a, [&](int i, int *L, Grp<kGroup> g) {
+        xfer_target<D, P, MIXED, UNIT, kGroup>(a, gp, i, L, g);
+    });
 }
 
 template <int D, bool UNIT>
@@ -282,6 +378,7 @@ int main(int argc, char **argv)
     a.r = r;
     a.k_cap = k_cap;
     a.words = k_cap < 2 ? 2 : k_cap;
+    a.stride = a.words | 1;
     a.svals = svals.data();
     a.nf = (int)nf;
     a.weight = weight;
@@ -311,8 +408,8 @@ int main(int argc, char **argv)
     }
 #undef DIMCASE
     std::fprintf(stderr, "work: walks %lld rows %lld candidates %lld per target: %.2f %.2f %.2f\n",
-                 pcms_emu_walks, pcms_emu_rows, pcms_emu_cands, (double)pcms_emu_walks / n_tgt,
-                 (double)pcms_emu_rows / n_tgt, (double)pcms_emu_cands / n_tgt);
+                 g_walks, g_rows, g_cands, (double)g_walks / n_tgt, (double)g_rows / n_tgt,
+                 (double)g_cands / n_tgt);
     FILE *o = std::fopen(argv[2], "wb");
     if (!o) die("cannot open output");
     if (op == 0) {

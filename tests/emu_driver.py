@@ -26,7 +26,7 @@ def build(force=False) -> str:
     if (not force and os.path.exists(EXE)
             and os.path.getmtime(EXE) >= max(os.path.getmtime(d) for d in DEPS)):
         return EXE
-    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
+    cmd = ["g++", "-std=c++20", "-O1", "-pthread", "-g", "-fno-omit-frame-pointer",
            "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
            "-DPCMS_HOST_EMULATION", "-I", os.path.join(ROOT, "include"),
            "-I", os.path.join(ROOT, "paper_2510_18838_amd", "csrc"), SRC, "-o", EXE + ".tmp"]
