@@ -30,6 +30,7 @@ namespace pcms {
 
 constexpr int kFieldChunk = 8;
 constexpr int kMaxRefine = 4;
+constexpr int kNbrBatch = 4;   // neighbours per lane whose loads are issued together
 
 template <int D, int P>
 struct Basis {
@@ -242,6 +243,33 @@ PCMS_HD PCMS_INLINE int nbr_target(const KArgs &a, const GridParams &gp, int i, 
     return st;
 }
 
+// Loads the coordinates of kept neighbours e0 + j G (j < kNbrBatch) of this
+// lane at once; slots past n repeat neighbour 0 and are flagged invalid.
+template <int D, int G, class S_>
+PCMS_HD PCMS_INLINE void load_neighbours(S_ &S, const double *__restrict__ spts, int e0, int n,
+                                         double (&sb)[kNbrBatch][D], bool (&ok)[kNbrBatch])
+{
+    int pe[kNbrBatch];
+    load_neighbours<D, G>(S, spts, e0, n, sb, ok, pe);
+}
+
+template <int D, int G, class S_>
+PCMS_HD PCMS_INLINE void load_neighbours(S_ &S, const double *__restrict__ spts, int e0, int n,
+                                         double (&sb)[kNbrBatch][D], bool (&ok)[kNbrBatch],
+                                         int (&pe)[kNbrBatch])
+{
+#pragma unroll
+    for (int j = 0; j < kNbrBatch; ++j) {
+        const int e = e0 + j * G;
+        ok[j] = e < n;
+        pe[j] = S.at(ok[j] ? e : 0);
+    }
+#pragma unroll
+    for (int j = 0; j < kNbrBatch; ++j)
+#pragma unroll
+        for (int k = 0; k < D; ++k) sb[j][k] = spts[(size_t)pe[j] * D + k];
+}
+
 // Per-neighbour local data: monomials p and weight w, in T.
 template <int D, int P, bool UNIT, typename T>
 PCMS_HD PCMS_INLINE void neighbour_data(const GridParams &gp, const double (&t)[D],
@@ -292,16 +320,22 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
             TA Gm[MM];
 #pragma unroll
             for (int j = 0; j < MM; ++j) Gm[j] = TA(0);
-            for (int e = g.q; e < n; e += G) {
-                TA p[M], w;
-                neighbour_data<D, P, UNIT, TA>(gp, S.t, a.spts + (size_t)S.at(e) * D, inv_h,
-                                               inv_r2, a.weight, p, w);
+            for (int e0 = g.q; e0 < n; e0 += G * kNbrBatch) {
+                double sb[kNbrBatch][D];
+                bool ok[kNbrBatch];
+                load_neighbours<D, G>(S, a.spts, e0, n, sb, ok);
 #pragma unroll
-                for (int u = 0; u < M; ++u) {
-                    TA wp = w * p[u];
+                for (int j = 0; j < kNbrBatch; ++j) {
+                    TA p[M], w;
+                    neighbour_data<D, P, UNIT, TA>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p, w);
+                    w = ok[j] ? w : TA(0);
 #pragma unroll
-                    for (int v = u; v < M; ++v)
-                        Gm[tri<M>(u, v)] = __builtin_fma(wp, p[v], Gm[tri<M>(u, v)]);
+                    for (int u = 0; u < M; ++u) {
+                        TA wp = w * p[u];
+#pragma unroll
+                        for (int v = u; v < M; ++v)
+                            Gm[tri<M>(u, v)] = __builtin_fma(wp, p[v], Gm[tri<M>(u, v)]);
+                    }
                 }
             }
 #pragma unroll
@@ -323,16 +357,22 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                 double res[M];
 #pragma unroll
                 for (int u = 0; u < M; ++u) res[u] = 0.0;
-                for (int e = g.q; e < n; e += G) {
-                    TA p[M], w;
-                    neighbour_data<D, P, UNIT, TA>(gp, S.t, a.spts + (size_t)S.at(e) * D, inv_h,
-                                                   inv_r2, a.weight, p, w);
-                    double py = 0.0;
+                for (int e0 = g.q; e0 < n; e0 += G * kNbrBatch) {
+                    double sb[kNbrBatch][D];
+                    bool ok[kNbrBatch];
+                    load_neighbours<D, G>(S, a.spts, e0, n, sb, ok);
 #pragma unroll
-                    for (int u = 0; u < M; ++u) py = __builtin_fma((double)p[u], y[u], py);
-                    double c = -(double)w * py;
+                    for (int j = 0; j < kNbrBatch; ++j) {
+                        TA p[M], w;
+                        neighbour_data<D, P, UNIT, TA>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p,
+                                                       w);
+                        double py = 0.0;
 #pragma unroll
-                    for (int u = 0; u < M; ++u) res[u] = __builtin_fma(c, (double)p[u], res[u]);
+                        for (int u = 0; u < M; ++u) py = __builtin_fma((double)p[u], y[u], py);
+                        const double c = ok[j] ? -(double)w * py : 0.0;
+#pragma unroll
+                        for (int u = 0; u < M; ++u) res[u] = __builtin_fma(c, (double)p[u], res[u]);
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < M; ++u)
@@ -366,19 +406,30 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                 // centring leaves the fit unchanged only without regularisation
                 fref[l] = (MIXED && a.lambda == 0.0 && l0 + l < a.nf) ? sv0[l0 + l] : 0.0;
             }
-            for (int e = g.q; e < n; e += G) {
-                const int pe = S.at(e);
-                TA p[M], w;
-                neighbour_data<D, P, UNIT, TA>(gp, S.t, a.spts + (size_t)pe * D, inv_h, inv_r2,
-                                               a.weight, p, w);
-                double py = 0.0;
+            for (int e0 = g.q; e0 < n; e0 += G * kNbrBatch) {
+                double sb[kNbrBatch][D];
+                bool ok[kNbrBatch];
+                int pe[kNbrBatch];
+                load_neighbours<D, G>(S, a.spts, e0, n, sb, ok, pe);
+                double fv[kNbrBatch][kFieldChunk];
 #pragma unroll
-                for (int u = 0; u < M; ++u) py = __builtin_fma((double)p[u], y[u], py);
-                const double N = (double)w * py;
-                const double *sv = a.svals + (size_t)pe * a.nf + l0;
+                for (int j = 0; j < kNbrBatch; ++j) {
+                    const double *sv = a.svals + (size_t)pe[j] * a.nf + l0;
 #pragma unroll
-                for (int l = 0; l < kFieldChunk; ++l)
-                    if (l0 + l < a.nf) acc[l] = __builtin_fma(N, sv[l] - fref[l], acc[l]);
+                    for (int l = 0; l < kFieldChunk; ++l) fv[j][l] = (l0 + l < a.nf) ? sv[l] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < kNbrBatch; ++j) {
+                    TA p[M], w;
+                    neighbour_data<D, P, UNIT, TA>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p, w);
+                    double py = 0.0;
+#pragma unroll
+                    for (int u = 0; u < M; ++u) py = __builtin_fma((double)p[u], y[u], py);
+                    const double N = ok[j] ? (double)w * py : 0.0;
+#pragma unroll
+                    for (int l = 0; l < kFieldChunk; ++l)
+                        acc[l] = __builtin_fma(N, fv[j][l] - fref[l], acc[l]);
+                }
             }
 #pragma unroll
             for (int l = 0; l < kFieldChunk; ++l) {

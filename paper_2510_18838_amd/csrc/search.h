@@ -38,10 +38,84 @@ PCMS_HD PCMS_INLINE double metric_d2(const double (&t)[D], const double *__restr
     return acc;
 }
 
+// Rows of a stencil walk: for radius rho around t, yields the rows (bucket
+// coordinates c_1..c_{d-1}) whose slab is within reach, with each row's
+// linear id and the c_0 range of the ball's chord in that slab.
+template <int D, bool UNIT>
+struct RowIter {
+    const GridParams &gp;
+    const double (&t)[D];
+    double rho2;
+    int a[D], b[D], c[D];
+    bool done;
+
+    PCMS_HD PCMS_INLINE RowIter(const GridParams &gp_, const double (&t_)[D], double rho2_)
+        : gp(gp_), t(t_), rho2(rho2_), done(false)
+    {
+        const double rho = sqrt(rho2);
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            double half = (UNIT ? rho : rho / gp.g[k]) * (1.0 + 1e-9) + fabs(t[k]) * 1e-15 + 1e-300;
+            a[k] = bucket_of(gp, k, t[k] - half);
+            b[k] = bucket_of(gp, k, t[k] + half);
+            c[k] = a[k];
+        }
+    }
+
+    // Next row within reach; false when the stencil is exhausted.
+    PCMS_HD PCMS_INLINE bool next(int &row, int &a0, int &b0)
+    {
+        while (!done) {
+            // squared metric distance from t to this row's slab (boxes widened
+            // slightly so rounding in the bucket assignment cannot hide a source)
+            double m2 = 0.0;
+            row = 0;
+#pragma unroll
+            for (int k = 1; k < D; ++k) {
+                double blo = gp.lo[k] + (double)c[k] * gp.w[k];
+                double bhi = blo + gp.w[k];
+                double pad = 1e-7 * gp.w[k];
+                // the first and last buckets also hold clamped coordinates
+                if (c[k] == 0) blo = -INFINITY;
+                if (c[k] == gp.n[k] - 1) bhi = INFINITY;
+                double dlt = fmax(fmax(blo - pad - t[k], t[k] - bhi - pad), 0.0);
+                if (!UNIT) dlt *= gp.g[k];
+                m2 = __builtin_fma(dlt, dlt, m2);
+                row += c[k] * gp.stride[k];
+            }
+            const bool reach = m2 <= rho2 * (1.0 + 1e-9);
+            if (reach) {
+                double rem2 = fmax(rho2 - m2 * (1.0 - 1e-9), 0.0);
+                double half0 = (UNIT ? sqrt(rem2) : sqrt(rem2) / gp.g[0]) * (1.0 + 1e-9) +
+                               fabs(t[0]) * 1e-15 + 1e-300;
+                a0 = bucket_of(gp, 0, t[0] - half0);
+                b0 = bucket_of(gp, 0, t[0] + half0);
+            }
+            // odometer over c_1..c_{d-1}, unrolled so c stays in registers
+            bool carry = true;
+#pragma unroll
+            for (int k = 1; k < D; ++k) {
+                if (carry) {
+                    if (c[k] < b[k]) {
+                        c[k]++;
+                        carry = false;
+                    } else {
+                        c[k] = a[k];
+                    }
+                }
+            }
+            if (carry) done = true;
+            if (reach) return true;
+        }
+        return false;
+    }
+};
+
 // Calls f(p, D, valid) for every sorted source p in the buckets that can hold
 // a source with D < rho2 (a superset of the ball), kBatch * G candidates per
 // step; every lane of the group calls f the same number of times, with valid
-// = false on the padding slots past a row's end.  rho2 may be +inf.
+// = false on the padding slots past a row's end.  rho2 may be +inf.  The next
+// row's bucket offsets are loaded while the current row is processed.
 template <int D, bool UNIT, int G, class F>
 PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs,
                               const double *__restrict__ spts, const double (&t)[D], double rho2,
@@ -51,75 +125,47 @@ PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs,
 #ifdef PCMS_HOST_EMULATION
     if (q == 0) ++pcms_emu_walks;
 #endif
-    const double rho = sqrt(rho2);
-    int a[D], b[D], c[D];
-#pragma unroll
-    for (int k = 1; k < D; ++k) {
-        double half = (UNIT ? rho : rho / gp.g[k]) * (1.0 + 1e-9) + fabs(t[k]) * 1e-15 + 1e-300;
-        a[k] = bucket_of(gp, k, t[k] - half);
-        b[k] = bucket_of(gp, k, t[k] + half);
-        c[k] = a[k];
+    RowIter<D, UNIT> it(gp, t, rho2);
+    int row, a0, b0;
+    bool have = it.next(row, a0, b0);
+    int beg = 0, end = 0;
+    if (have) {
+        beg = cs[row + a0];
+        end = cs[row + b0 + 1];
     }
-    for (;;) {
-        // squared metric distance from t to this row's slab (boxes widened
-        // slightly so rounding in the bucket assignment cannot hide a source)
-        double m2 = 0.0;
-        int row = 0;
-#pragma unroll
-        for (int k = 1; k < D; ++k) {
-            double blo = gp.lo[k] + (double)c[k] * gp.w[k];
-            double bhi = blo + gp.w[k];
-            double pad = 1e-7 * gp.w[k];
-            // the first and last buckets also hold clamped coordinates
-            if (c[k] == 0) blo = -INFINITY;
-            if (c[k] == gp.n[k] - 1) bhi = INFINITY;
-            double dlt = fmax(fmax(blo - pad - t[k], t[k] - bhi - pad), 0.0);
-            if (!UNIT) dlt *= gp.g[k];
-            m2 = __builtin_fma(dlt, dlt, m2);
-            row += c[k] * gp.stride[k];
+    while (have) {
+        int nbeg = 0, nend = 0;
+        const bool nhave = it.next(row, a0, b0);
+        if (nhave) {
+            nbeg = cs[row + a0];
+            nend = cs[row + b0 + 1];
         }
 #ifdef PCMS_HOST_EMULATION
-        if (q == 0) ++pcms_emu_rows;
-#endif
-        if (m2 <= rho2 * (1.0 + 1e-9)) {
-            double rem2 = fmax(rho2 - m2 * (1.0 - 1e-9), 0.0);
-            double half0 = (UNIT ? sqrt(rem2) : sqrt(rem2) / gp.g[0]) * (1.0 + 1e-9) +
-                           fabs(t[0]) * 1e-15 + 1e-300;
-            int a0 = bucket_of(gp, 0, t[0] - half0);
-            int b0 = bucket_of(gp, 0, t[0] + half0);
-            const int beg = cs[row + a0];
-            const int end = cs[row + b0 + 1];
-#ifdef PCMS_HOST_EMULATION
-            if (q == 0) pcms_emu_cands += end - beg;
-#endif
-            for (int p0 = beg; p0 < end; p0 += kBatch * G) {
-                // slot j of lane q is candidate p0 + j*G + q: the group's
-                // loads of one slot are contiguous
-                double sb[kBatch][D];
-                int pp[kBatch];
-                bool ok[kBatch];
-#pragma unroll
-                for (int j = 0; j < kBatch; ++j) {
-                    pp[j] = p0 + j * G + q;
-                    ok[j] = pp[j] < end;
-                    const int pl = ok[j] ? pp[j] : beg;
-#pragma unroll
-                    for (int k = 0; k < D; ++k) sb[j][k] = spts[(size_t)pl * D + k];
-                }
-#pragma unroll
-                for (int j = 0; j < kBatch; ++j) f(pp[j], metric_d2<D, UNIT>(t, sb[j], gp), ok[j]);
-            }
+        if (q == 0) {
+            ++pcms_emu_rows;
+            pcms_emu_cands += end - beg;
         }
-        int k = 1;
-        while (k < D) {
-            if (c[k] < b[k]) {
-                c[k]++;
-                break;
+#endif
+        for (int p0 = beg; p0 < end; p0 += kBatch * G) {
+            // slot j of lane q is candidate p0 + j*G + q: the group's loads of
+            // one slot are contiguous
+            double sb[kBatch][D];
+            int pp[kBatch];
+            bool ok[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                pp[j] = p0 + j * G + q;
+                ok[j] = pp[j] < end;
+                const int pl = ok[j] ? pp[j] : beg;
+#pragma unroll
+                for (int k = 0; k < D; ++k) sb[j][k] = spts[(size_t)pl * D + k];
             }
-            c[k] = a[k];
-            k++;
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) f(pp[j], metric_d2<D, UNIT>(t, sb[j], gp), ok[j]);
         }
-        if (k >= D) break;
+        beg = nbeg;
+        end = nend;
+        have = nhave;
     }
 }
 
@@ -184,7 +230,9 @@ struct Search {
     {
         int n = 0;
         each(r2, [&](int p, double d2, bool ok) {
-            const bool acc = ok && d2 < r2;
+            // bitwise '&': d2 is needed whatever ok is, so the compiler keeps
+            // the batch's loads together instead of sinking one into a branch
+            const bool acc = ok & (d2 < r2);
             const unsigned m = g.ballot(acc);
             if (acc) {
                 const int pos = n + g.below(m);
@@ -216,16 +264,19 @@ struct Search {
 #pragma unroll
             for (int j = 1; j < D; ++j) row += c[j] * gp.stride[j];
             count += cs[row + b[0] + 1] - cs[row + a[0]];
-            int j = 1;
-            while (j < D) {
-                if (c[j] < b[j]) {
-                    c[j]++;
-                    break;
+            bool carry = true;
+#pragma unroll
+            for (int j = 1; j < D; ++j) {
+                if (carry) {
+                    if (c[j] < b[j]) {
+                        c[j]++;
+                        carry = false;
+                    } else {
+                        c[j] = a[j];
+                    }
                 }
-                c[j] = a[j];
-                j++;
             }
-            if (j >= D) break;
+            if (carry) break;
         }
         // unit-ball volume pi^(D/2) / Gamma(D/2 + 1)
         const double vball = D == 1 ? 2.0 : D == 2 ? M_PI : D == 3 ? 4.18879020478639098
@@ -246,8 +297,8 @@ struct Search {
     {
         int below = 0, n = 0;
         each(hi, [&](int, double d2, bool ok) {
-            below += ok && d2 < lo;
-            const bool in = ok && d2 >= lo && d2 < hi;
+            below += ok & (d2 < lo);
+            const bool in = ok & (d2 >= lo) & (d2 < hi);
             const unsigned m = g.ballot(in);
             if (in) {
                 const int pos = n + g.below(m);
@@ -334,7 +385,7 @@ struct Search {
             double vmin = h0;   // smallest D in [lo, hi) and its multiplicity
             int neq = 0;
             each(h0, [&](int, double d2, bool ok) {
-                if (ok && d2 >= l0 && d2 < h0) {
+                if (ok & (d2 >= l0) & (d2 < h0)) {
 #pragma unroll
                     for (int j = 0; j < NB; ++j) cnt[j] += d2 < sp[j];
                     if (d2 < vmin) {
@@ -408,14 +459,14 @@ struct Search {
         const double vnext = nextafter(v, INFINITY);
         int n = 0, c_eq = 0;
         each(vnext, [&](int p, double d2, bool ok) {
-            const bool acc = ok && d2 < v;
+            const bool acc = ok & (d2 < v);
             const unsigned m = g.ballot(acc);
             if (acc) {
                 const int pos = n + g.below(m);
                 if (pos < k_cap) at(pos) = p;
             }
             n += __builtin_popcount(m);
-            c_eq += ok && d2 == v;
+            c_eq += ok & (d2 == v);
         });
         g.sync();
         c_eq = g.sum(c_eq);
@@ -427,7 +478,7 @@ struct Search {
             for (int r = 0; r < need; ++r) {
                 int best = 0x7fffffff;
                 each(vnext, [&](int p, double d2, bool ok) {
-                    if (ok && d2 == v) {
+                    if (ok & (d2 == v)) {
                         const int j = perm[p];
                         if (j > prev && j < best) best = j;
                     }
@@ -437,7 +488,7 @@ struct Search {
             jthr = prev;
         }
         each(vnext, [&](int p, double d2, bool ok) {
-            const bool acc = ok && d2 == v && perm[p] <= jthr;
+            const bool acc = ok & (d2 == v) && perm[p] <= jthr;
             const unsigned m = g.ballot(acc);
             if (acc) {
                 const int pos = n + g.below(m);
