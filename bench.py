@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (profiling aid)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes three times "
+                         "(calibrates the HBM byte counters against a known traffic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -94,6 +97,15 @@ def main():
     from paper_2510_18838_amd import pcms, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_bytes:
+        n = args.copy_bytes // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {8 * n} bytes three times")
+        return
     pcms.lib()
     dev = torch.device("cuda:0")
     n = int(4_000_000 * args.scale)

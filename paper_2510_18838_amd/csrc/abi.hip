@@ -252,7 +252,7 @@ static pcms_status grid_create(int64_t n_src, int32_t dim, const double *inv_sca
         (e = hipMalloc(&g->cell_start, sizeof(int) * ((size_t)g->n_cells_cap + 1))) != hipSuccess ||
         (e = hipMalloc(&g->perm, sizeof(int) * (size_t)n_src)) != hipSuccess ||
         (e = hipMalloc(&g->iperm, sizeof(int) * (size_t)n_src)) != hipSuccess ||
-        (e = hipMalloc(&g->spts, sizeof(double) * (size_t)n_src * dim)) != hipSuccess) {
+        (e = hipMalloc(&g->spts, sizeof(double) * (size_t)n_src * padded_dim(dim))) != hipSuccess) {
         grid_alloc_free(g);
         return hip_fail(e, "hipMalloc(grid)");
     }
@@ -405,7 +405,7 @@ pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, con
     size_t o_perm = o_cs + ((sizeof(int) * ((size_t)g.n_cells_cap + 1) + 255) & ~(size_t)255);
     size_t o_iperm = o_perm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
     size_t o_spts = o_iperm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
-    size_t bytes = o_spts + sizeof(double) * (size_t)n_src * dim;
+    size_t bytes = o_spts + sizeof(double) * (size_t)n_src * padded_dim(dim);
     if ((st = scratch_alloc(&sc.p, bytes, s)) != PCMS_OK) return st;
     g.params = (GridParams *)sc.p;
     g.cell_start = (int *)((char *)sc.p + o_cs);

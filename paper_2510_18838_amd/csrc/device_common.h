@@ -161,6 +161,74 @@ PCMS_HD PCMS_INLINE unsigned bucket_key(const GridParams &p, const double *x)
     return (unsigned)id;
 }
 
+// Processing order of the targets: tiles of 8 buckets per side (in every
+// dimension with at least 16 buckets) in row-major order, and Morton order
+// of the buckets inside a tile, so that a wave's consecutive targets cover a
+// compact block of buckets.  Keys are below tile_key_bound(n_cells, dim).
+PCMS_HD PCMS_INLINE unsigned target_key(const GridParams &p, const double *x)
+{
+    unsigned tile = 0, tstride = 1, local = 0;
+    int nt = 0;   // tiled dimensions so far
+    int tiled[kMaxDim], c[kMaxDim];
+    for (int k = 0; k < p.dim; ++k) {
+        c[k] = bucket_of(p, k, x[k]);
+        tiled[k] = p.n[k] >= 16;
+        nt += tiled[k];
+    }
+    int r = 0;
+    for (int k = 0; k < p.dim; ++k) {
+        const int sh = tiled[k] ? 3 : 0;
+        tile += (unsigned)(c[k] >> sh) * tstride;
+        tstride *= (unsigned)((p.n[k] + (1 << sh) - 1) >> sh);
+        if (tiled[k]) {
+            for (int b = 0; b < 3; ++b) local |= (unsigned)((c[k] >> b) & 1) << (b * nt + r);
+            ++r;
+        }
+    }
+    return (tile << (3 * nt)) | local;
+}
+
+// Upper bound of the target keys: each tiled dimension rounds its bucket
+// count up to a multiple of 8 (at most 23/16 of it, as it has >= 16).
+inline double tile_key_bound(double n_cells, int dim)
+{
+    double f = 1.0;
+    for (int k = 0; k < dim; ++k) f *= 23.0 / 16.0;
+    return n_cells * f + 1.0;
+}
+
+// Sorted source coordinates are stored with an even stride (3-D points take
+// four doubles), so that every point starts on a 16-byte boundary and loads
+// as whole 16-byte words.
+PCMS_HD PCMS_INLINE constexpr int padded_dim(int d) { return (d + 1) & ~1; }
+
+template <int D>
+PCMS_HD PCMS_INLINE void load_src(const double *__restrict__ spts, int p, double (&s)[D])
+{
+    constexpr int DP = padded_dim(D);
+    const double *b = spts + (size_t)p * DP;
+#ifdef PCMS_HOST_EMULATION
+    for (int k = 0; k < D; ++k) s[k] = b[k];
+#else
+#pragma unroll
+    for (int j = 0; j < DP / 2; ++j) {
+        const double2 v = reinterpret_cast<const double2 *>(b)[j];
+        s[2 * j] = v.x;
+        if (2 * j + 1 < D) s[2 * j + 1] = v.y;
+    }
+#endif
+}
+
+// Atomic add to a word of the block's LDS.
+PCMS_HD PCMS_INLINE void lds_add(int *w, int v)
+{
+#ifdef PCMS_HOST_EMULATION
+    __atomic_fetch_add(w, v, __ATOMIC_RELAXED);
+#else
+    atomicAdd(w, v);
+#endif
+}
+
 // --- lane groups -----------------------------------------------------------
 // G consecutive lanes of a wave (G a power of two, <= 16) cooperate on one
 // target.  Group operations must be reached by all G lanes together (the

@@ -196,8 +196,11 @@ PCMS_HD PCMS_INLINE int select_target(Search<D, UNIT, G> &S, const KArgs &a, int
         }
         if (n_found < a.n_min) st = PCMS_TGT_RADIUS_EXHAUSTED;
     } else {
-        r2 = S.knn_r2(a.k);
-        n_found = S.collect(r2);
+        // n_found < k <= k_cap + 1 on the two-walk path, so no cap applies
+        if (!(a.k <= a.k_cap + 1 && S.knn_select(a.k, r2, n_found))) {
+            r2 = S.knn_r2(a.k);
+            n_found = S.collect(r2);
+        }
     }
     n_kept = min(n_found, a.k_cap);
     if (n_found > a.k_cap) {
@@ -265,9 +268,7 @@ PCMS_HD PCMS_INLINE void load_neighbours(S_ &S, const double *__restrict__ spts,
         pe[j] = S.at(ok[j] ? e : 0);
     }
 #pragma unroll
-    for (int j = 0; j < kNbrBatch; ++j)
-#pragma unroll
-        for (int k = 0; k < D; ++k) sb[j][k] = spts[(size_t)pe[j] * D + k];
+    for (int j = 0; j < kNbrBatch; ++j) load_src<D>(spts, pe[j], sb[j]);
 }
 
 // Per-neighbour local data: monomials p and weight w, in T.

@@ -122,6 +122,23 @@ __global__ void k_bucket_keys(const GridParams *__restrict__ gp, const double *_
     }
 }
 
+// Processing-order keys of the targets (tiled Morton order, target_key).
+template <int D>
+__global__ void k_target_keys(const GridParams *__restrict__ gp, const double *__restrict__ pts,
+                              int64_t n, unsigned *__restrict__ keys, int *__restrict__ vals)
+{
+    GridParams p = *gp;
+    p.dim = D;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double x[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = pts[i * D + k];
+        keys[i] = target_key(p, x);
+        vals[i] = (int)i;
+    }
+}
+
 template <int D>
 void launch_bucket_keys(const GridParams *gp, const double *pts, int64_t n, unsigned *keys,
                         int *vals, int blocks, hipStream_t s)
@@ -334,13 +351,16 @@ __global__ void k_cell_start(const GridParams *__restrict__ gp, const unsigned *
     }
 }
 
+// Sorted coordinates with the padded stride (padding written as zero) and
+// the inverse permutation.
 __global__ void k_gather_pts(const double *__restrict__ src, const int *__restrict__ perm,
                              int64_t n, int dim, double *__restrict__ spts, int *__restrict__ iperm)
 {
+    const int dp = padded_dim(dim);
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
         int64_t j = perm[p];
-        for (int k = 0; k < dim; ++k) spts[p * dim + k] = src[j * dim + k];
+        for (int k = 0; k < dp; ++k) spts[p * dp + k] = k < dim ? src[j * dim + k] : 0.0;
         iperm[j] = (int)p;
     }
 }
@@ -437,9 +457,27 @@ pcms_status sort_targets(const Grid *grid, const double *tgt, int64_t n_tgt, int
     int *hist = (int *)cur;
     cur += sizeof(int) * (size_t)256 * nb;
     int *scan_scratch = (int *)cur;
-    if ((st = bucket_keys(grid->dim, grid->params, tgt, n, k0, tperm, grid_blocks(n, 256), s)) != PCMS_OK)
-        return st;
-    st = radix_sort(k0, tperm, k1, v1, n, key_bits(grid->n_cells_cap), hist, scan_scratch, s);
+    // tiled Morton order when its keys fit 32 bits, else bucket order
+    const double bound = tile_key_bound((double)grid->n_cells_cap, grid->dim);
+    int bits;
+    if (bound < 4294967295.0) {
+        const int blocks = grid_blocks(n, 256);
+        switch (grid->dim) {
+        case 1: k_target_keys<1><<<blocks, 256, 0, s>>>(grid->params, tgt, n, k0, tperm); break;
+        case 2: k_target_keys<2><<<blocks, 256, 0, s>>>(grid->params, tgt, n, k0, tperm); break;
+        case 3: k_target_keys<3><<<blocks, 256, 0, s>>>(grid->params, tgt, n, k0, tperm); break;
+        case 4: k_target_keys<4><<<blocks, 256, 0, s>>>(grid->params, tgt, n, k0, tperm); break;
+        default: k_target_keys<5><<<blocks, 256, 0, s>>>(grid->params, tgt, n, k0, tperm); break;
+        }
+        PCMS_HIP(hipGetLastError());
+        bits = 0;
+        while (bits < 32 && (double)(1ull << bits) < bound) ++bits;
+    } else {
+        if ((st = bucket_keys(grid->dim, grid->params, tgt, n, k0, tperm, grid_blocks(n, 256), s)) != PCMS_OK)
+            return st;
+        bits = key_bits(grid->n_cells_cap);
+    }
+    st = radix_sort(k0, tperm, k1, v1, n, bits, hist, scan_scratch, s);
     if (st != PCMS_OK) return st;
     scratch_free(raw, s);
     return PCMS_OK;

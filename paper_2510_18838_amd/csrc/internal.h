@@ -21,7 +21,7 @@ struct Grid {
     int *cell_start;      // device [n_cells_cap + 1]
     int *perm;            // device [n_src]: sorted position -> source index
     int *iperm;           // device [n_src]: source index -> sorted position
-    double *spts;         // device [n_src * dim]: sorted coordinates
+    double *spts;         // device [n_src * padded_dim(dim)]: sorted coordinates
     int device;
 };
 

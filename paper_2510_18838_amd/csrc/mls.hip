@@ -1,5 +1,5 @@
 // Neighbour-list and field-transfer kernels: one lane per target, targets in
-// bucket order so that the lanes of a wave search overlapping stencils.  The
+// tiled Morton order so that the lanes of a wave search overlapping stencils.  The
 // per-target work (search, moment assembly, Cholesky, evaluation) is in
 // fit.h / search.h; this file holds the kernels and their launchers.
 #include <hip/hip_runtime.h>
@@ -35,9 +35,12 @@ __device__ __forceinline__ void add_summary(int32_t *summary, int st, bool activ
     }
 }
 
-// G consecutive lanes per target; the block's targets are consecutive in
-// bucket order and each owns `stride` LDS words.
-constexpr int kGroup = 4;
+// Lanes per target (G consecutive lanes of a wave); the block's targets are
+// consecutive in processing order and each owns `stride` LDS words.
+#ifndef PCMS_LANES_PER_TARGET
+#define PCMS_LANES_PER_TARGET 1
+#endif
+constexpr int kGroup = PCMS_LANES_PER_TARGET;
 
 template <int D, bool UNIT, int G>
 __global__ void __launch_bounds__(256) k_neighbors(KArgs a)

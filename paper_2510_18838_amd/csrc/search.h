@@ -156,9 +156,7 @@ PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs,
             for (int j = 0; j < kBatch; ++j) {
                 pp[j] = p0 + j * G + q;
                 ok[j] = pp[j] < end;
-                const int pl = ok[j] ? pp[j] : beg;
-#pragma unroll
-                for (int k = 0; k < D; ++k) sb[j][k] = spts[(size_t)pl * D + k];
+                load_src<D>(spts, ok[j] ? pp[j] : beg, sb[j]);
             }
 #pragma unroll
             for (int j = 0; j < kBatch; ++j) f(pp[j], metric_d2<D, UNIT>(t, sb[j], gp), ok[j]);
@@ -201,6 +199,19 @@ struct Search {
     {
         unsigned long long lo = (unsigned)at(2 * j);
         unsigned long long hi = (unsigned)at(2 * j + 1);
+        return __builtin_bit_cast(double, (hi << 32) | lo);
+    }
+    // a double in words w, w + 1 (any w)
+    PCMS_HD PCMS_INLINE void wstore(int w, double v)
+    {
+        unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
+        at(w) = (int)(unsigned)(bits & 0xffffffffull);
+        at(w + 1) = (int)(unsigned)(bits >> 32);
+    }
+    PCMS_HD PCMS_INLINE double wload(int w)
+    {
+        unsigned long long lo = (unsigned)at(w);
+        unsigned long long hi = (unsigned)at(w + 1);
         return __builtin_bit_cast(double, (hi << 32) | lo);
     }
 
@@ -330,6 +341,112 @@ struct Search {
             }
         }
         return g.min(ans);
+    }
+
+    // kNN selection in two walks, for k <= k_cap + 1.  The first walk, over
+    // the ball of radius (1 + 0.3) g (g the bucket-count estimate of the
+    // radius), counts the sources below lo = ((1 - 0.22) g)^2 and histograms
+    // those in [lo, hi = ((1 + 0.3) g)^2) into nb bins of equal width in D
+    // (the target's first nb words serve as the bins).  The second walk
+    // lists, in walk order, every source of a lower bin (or below lo) and
+    // buffers the (D, index) pairs of the bin holding the k-th at the end of
+    // the words; the k-th is ranked there and the buffered sources below it
+    // complete the list.  Both walks classify a source with the same
+    // expression of its D, so their counts agree exactly.  On success r2 is
+    // the k-th smallest D, the list holds every source with D < r2 and
+    // n_found their count (< k); returns false when the k-th lies outside
+    // [lo, hi) or the bin does not fit the words, leaving the general path
+    // to the caller.
+    PCMS_HD bool knn_select(int k, double &r2, int &n_found)
+    {
+        const double gr = knn_radius_guess(k);
+        const double lo = (0.78 * gr) * (0.78 * gr), hi = (1.3 * gr) * (1.3 * gr);
+        const int nb = words < 48 ? words : 48;
+        const double bw = (hi - lo) / nb, ibw = 1.0 / bw;
+        // -1 below lo, the bin in [lo, hi), nb at or above hi
+        auto key = [&](double d2) {
+            return d2 < lo ? -1 : d2 < hi ? min((int)((d2 - lo) * ibw), nb - 1) : nb;
+        };
+        for (int j = g.q; j < nb; j += G) at(j) = 0;
+        g.sync();
+        int below = 0;
+        each(hi, [&](int, double d2, bool ok) {
+            const int kk = key(d2);
+            below += ok & (kk < 0);
+            if (ok & (kk >= 0) & (kk < nb)) lds_add(&at(kk), 1);
+        });
+        g.sync();
+        const int c_lo = g.sum(below);
+        int b = -1, c_b = 0, n_b = 0;
+        if (c_lo < k) {
+            int cum = c_lo;
+            for (int j = 0; j < nb; ++j) {
+                const int cj = at(j);
+                if (b < 0 && cum + cj >= k) {
+                    b = j;
+                    c_b = cum;
+                    n_b = cj;
+                }
+                cum += cj;
+            }
+        }
+        g.sync();   // every lane has read the bins before the list overwrites them
+        // the appended entries [c_b, c_b + n_b) must stay below the buffer
+        if (b < 0 || c_b + 4 * n_b > words) return false;
+        const double rho2 = b == nb - 1 ? hi : fmin(hi, (lo + (double)(b + 1) * bw) * (1.0 + 1e-12));
+        int n = 0, m = 0;
+        each(rho2, [&](int p, double d2, bool ok) {
+            const int kk = key(d2);
+            const bool in = ok & (kk < b);
+            const bool bb = ok & (kk == b);
+            const unsigned mi = g.ballot(in), mb = g.ballot(bb);
+            if (in) {
+                const int pos = n + g.below(mi);
+                if (pos < c_b) at(pos) = p;
+            }
+            if (bb) {
+                const int j = m + g.below(mb);
+                if (j < n_b) {
+                    const int w = words - 3 * (j + 1);
+                    wstore(w, d2);
+                    at(w + 2) = p;
+                }
+            }
+            n += __builtin_popcount(mi);
+            m += __builtin_popcount(mb);
+        });
+        g.sync();
+        if (n != c_b || m != n_b) return false;   // cannot happen: same sources, same key
+        // r-th smallest (1-based) of the bin, ranked by the lanes in turn
+        const int r = k - c_b;
+        double ans = INFINITY;
+        for (int a0 = 0; a0 < n_b; a0 += G) {
+            const int a = a0 + g.q;
+            if (a < n_b) {
+                const double v = wload(words - 3 * (a + 1));
+                int less = 0, le = 0;
+                for (int j = 0; j < n_b; ++j) {
+                    const double x = wload(words - 3 * (j + 1));
+                    less += x < v;
+                    le += x <= v;
+                }
+                if (less < r && r <= le) ans = v;
+            }
+        }
+        r2 = g.min(ans);
+        // append the bin's sources below r2, in walk order
+        int cnt = c_b;
+        for (int j0 = 0; j0 < n_b; j0 += G) {
+            const int j = j0 + g.q;
+            const bool take = j < n_b && wload(words - 3 * (min(j, n_b - 1) + 1)) < r2;
+            const int p = take ? at(words - 3 * (j + 1) + 2) : 0;
+            const unsigned mt = g.ballot(take);
+            if (take) at(cnt + g.below(mt)) = p;
+            cnt += __builtin_popcount(mt);
+        }
+        g.sync();
+        n_found = cnt;
+        return true;
     }
 
     // Squared distance of the k-th nearest source.  One walk counts the

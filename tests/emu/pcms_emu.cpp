@@ -213,11 +213,10 @@ int key_bits(int cap)
     return b;
 }
 
-constexpr int kGroup = 4;   // lanes per target, as in the kernels
-
-// Runs body(i, L, grp) for every target on kGroup threads (lane q = thread q),
-// each target with its own poisoned LDS words; reports work per wave.
-template <class Body>
+// Runs body(i, L, grp) for every target on G threads (lane q = thread q),
+// each target with its own poisoned LDS words; reports work per wave.  The
+// kernels run one lane per target; G > 1 exercises the cooperative paths.
+template <int kGroup, class Body>
 void run_groups(const KArgs &a, Body body)
 {
     std::vector<int> lds((size_t)std::max(a.n_tgt, 1) * a.words, 0x7f7f7f7f);
@@ -262,31 +261,36 @@ void run_groups(const KArgs &a, Body body)
                      mw / nw, mc / nw, (double)g_walks / a.n_tgt, (double)g_cands / a.n_tgt);
 }
 
-template <int D, bool UNIT>
-void run_nbr(const KArgs &a, const GridParams &gp, int)
+template <int D, bool UNIT, int G>
+void run_nbr(const KArgs &a, const GridParams &gp)
 {
-    run_groups(a, [&](int i, int *L, Grp<kGroup> g) { nbr_target<D, UNIT, kGroup>(a, gp, i, L, g); });
+    run_groups<G>(a, [&](int i, int *L, Grp<G> g) { nbr_target<D, UNIT, G>(a, gp, i, L, g); });
 }
 
-template <int D, int P, bool MIXED, bool UNIT>
-void run_xfer(const KArgs &a, const GridParams &gp, int)
+template <int D, int P, bool MIXED, bool UNIT, int G>
+void run_xfer(const KArgs &a, const GridParams &gp)
 {
-    run_groups(a, [&](int i, int *L, Grp<kGroup> g) {
-        xfer_target<D, P, MIXED, UNIT, kGroup>(a, gp, i, L, g);
-    });
+    run_groups<G>(a, [&](int i, int *L, Grp<G> g) { xfer_target<D, P, MIXED, UNIT, G>(a, gp, i, L, g); });
 }
 
-template <int D, bool UNIT>
-void dispatch(int op, const KArgs &a, const GridParams &gp, int block, int degree, bool mixed)
+template <int D, bool UNIT, int G>
+void dispatch_g(int op, const KArgs &a, const GridParams &gp, int degree, bool mixed)
 {
-    if (op == 0) return run_nbr<D, UNIT>(a, gp, block);
+    if (op == 0) return run_nbr<D, UNIT, G>(a, gp);
 #define X(PP)                                                                  \
     if (degree == PP) {                                                        \
-        if (mixed) return run_xfer<D, PP, true, UNIT>(a, gp, block);           \
-        return run_xfer<D, PP, false, UNIT>(a, gp, block);                     \
+        if (mixed) return run_xfer<D, PP, true, UNIT, G>(a, gp);               \
+        return run_xfer<D, PP, false, UNIT, G>(a, gp);                         \
     }
     X(0) X(1) X(2)
 #undef X
+}
+
+template <int D, bool UNIT>
+void dispatch(int op, const KArgs &a, const GridParams &gp, int group, int degree, bool mixed)
+{
+    if (group == 4) return dispatch_g<D, UNIT, 4>(op, a, gp, degree, mixed);
+    return dispatch_g<D, UNIT, 1>(op, a, gp, degree, mixed);
 }
 
 }  // namespace
@@ -302,7 +306,7 @@ int main(int argc, char **argv)
     const int64_t n_src = rd.i64(), dim = rd.i64(), n_tgt = rd.i64(), nf = rd.i64();
     const int degree = (int)rd.i64(), mode = (int)rd.i64(), k = (int)rd.i64();
     const int n_min = (int)rd.i64(), max_iter = (int)rd.i64(), k_cap = (int)rd.i64();
-    const int weight = (int)rd.i64(), precision = (int)rd.i64(), block = (int)rd.i64();
+    const int weight = (int)rd.i64(), precision = (int)rd.i64(), group = (int)rd.i64();
     const double r = rd.f64(), lambda = rd.f64(), cell_width = rd.f64(), ppc = rd.f64();
     double g[kMaxDim];
     for (int q = 0; q < kMaxDim; ++q) g[q] = rd.f64();
@@ -348,17 +352,25 @@ int main(int argc, char **argv)
     }
     // the kernels may read only [0, n_cells]: keep exactly that for the sanitiser
     cs = std::vector<int>(cs.begin(), cs.begin() + gp.n_cells + 1);
-    std::vector<double> spts((size_t)(n_src * dim));
+    const int dp = padded_dim(dim);
+    std::vector<double> spts((size_t)(n_src * dp), 0.0);
     for (int64_t p = 0; p < n_src; ++p)
-        for (int q = 0; q < dim; ++q) spts[p * dim + q] = src[(size_t)perm[p] * dim + q];
-    // targets
+        for (int q = 0; q < dim; ++q) spts[p * dp + q] = src[(size_t)perm[p] * dim + q];
+    // targets, in the kernels' processing order
     std::vector<unsigned> tkeys(n_tgt);
     std::vector<int> tperm(n_tgt);
+    const double bound = tile_key_bound((double)cap, dim);
+    const bool tiled = bound < 4294967295.0;
     for (int64_t i = 0; i < n_tgt; ++i) {
-        tkeys[i] = bucket_key(gp, &tgt[i * dim]);
+        tkeys[i] = tiled ? target_key(gp, &tgt[i * dim]) : bucket_key(gp, &tgt[i * dim]);
         tperm[i] = (int)i;
     }
-    radix_sort_emu(tkeys, tperm, key_bits(cap));
+    int tbits = key_bits(cap);
+    if (tiled) {
+        tbits = 0;
+        while (tbits < 32 && (double)(1ull << tbits) < bound) ++tbits;
+    }
+    radix_sort_emu(tkeys, tperm, tbits);
     std::vector<double> svals((size_t)(n_src * nf));
     for (int64_t p = 0; p < n_src; ++p)
         for (int l = 0; l < nf; ++l) svals[p * nf + l] = vals[(size_t)l * n_src + perm[p]];
@@ -399,8 +411,8 @@ int main(int argc, char **argv)
     const bool mixed = precision != PCMS_FP64;
 #define DIMCASE(DD)                                                                 \
     case DD:                                                                        \
-        if (unit) dispatch<DD, true>(op, a, gp, block, degree, mixed);              \
-        else dispatch<DD, false>(op, a, gp, block, degree, mixed);                  \
+        if (unit) dispatch<DD, true>(op, a, gp, group, degree, mixed);              \
+        else dispatch<DD, false>(op, a, gp, group, degree, mixed);                  \
         break;
     switch (dim) {
         DIMCASE(1) DIMCASE(2) DIMCASE(3) DIMCASE(4) DIMCASE(5)

@@ -47,8 +47,9 @@ def _cell_spec(prob):
     return cf * prob.radius, 0.0
 
 
-def run(prob, op, precision=0, weight=0, lam=0.0, block=64, tgt=None):
-    """op 0: neighbour lists; op 1: transfer.  Returns a dict like the GPU helpers."""
+def run(prob, op, precision=0, weight=0, lam=0.0, group=1, tgt=None):
+    """op 0: neighbour lists; op 1: transfer; group: lanes per target (1, as
+    in the kernels, or 4).  Returns a dict like the GPU helpers."""
     exe = build()
     t = prob.tgt if tgt is None else tgt
     n_src, dim = prob.src.shape
@@ -59,7 +60,7 @@ def run(prob, op, precision=0, weight=0, lam=0.0, block=64, tgt=None):
     if prob.inv_scale is not None:
         g[:dim] = prob.inv_scale
     hdr = np.array([0x50434d53454d55, op, n_src, dim, n_tgt, nf, prob.degree, prob.mode, prob.k,
-                    prob.n_min, prob.max_iter, prob.k_cap, weight, precision, block], np.int64)
+                    prob.n_min, prob.max_iter, prob.k_cap, weight, precision, group], np.int64)
     dbl = np.array([prob.radius, lam, cw, ppc, *g], np.float64)
     with tempfile.TemporaryDirectory() as d:
         fin, fout = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")

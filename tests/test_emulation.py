@@ -12,14 +12,19 @@ from paper_2510_18838_amd import synth
 
 
 class EmuBackend:
+    def __init__(self, group=1):
+        self.group = group
+
     def neighbors(self, prob):
-        return emu_driver.run(prob, 0)
+        return emu_driver.run(prob, 0, group=self.group)
 
     def transfer(self, prob, precision, weight=0, lam=0.0, block=64):
-        return emu_driver.run(prob, 1, precision=precision, weight=weight, lam=lam, block=block)
+        return emu_driver.run(prob, 1, precision=precision, weight=weight, lam=lam,
+                              group=self.group)
 
 
-BE = EmuBackend()
+BE = EmuBackend(1)    # one lane per target, as the kernels run
+BE4 = EmuBackend(4)   # four cooperating lanes: the group collectives
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -61,8 +66,17 @@ def test_emu_edge_cases():
     C.case_tight_caps(BE)
 
 
-def test_emu_block_shapes():
+def test_emu_lane_groups():
+    """Four cooperating lanes per target give the same lists and statuses,
+    and values within rounding, as one lane."""
+    C.case_c1(BE4)
+    C.case_ties(BE4)
+    C.case_tight_caps(BE4)
+    C.case_scaled(BE4, "c3", small=True)
     p = synth.c1()
-    a = BE.transfer(p, 0, block=64)
-    b = BE.transfer(p, 0, block=256)
-    assert (a["status"] == b["status"]).all()
+    a, b = BE.neighbors(p), BE4.neighbors(p)
+    for key in ("n_kept", "n_found", "r2", "status"):
+        assert (a[key] == b[key]).all(), key
+    for i in range(p.tgt.shape[0]):
+        n = a["n_kept"][i]
+        assert (a["nbr"][i, :n] == b["nbr"][i, :n]).all()
