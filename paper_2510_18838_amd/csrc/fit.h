@@ -30,7 +30,6 @@ namespace pcms {
 
 constexpr int kFieldChunk = 8;
 constexpr int kMaxRefine = 4;
-constexpr int kNbrBatch = 4;   // neighbours per lane whose loads are issued together
 
 template <int D, int P>
 struct Basis {
@@ -174,6 +173,17 @@ struct KArgs {
     int32_t *summary;
 };
 
+// LDS words of a target: its kept list (at most k_cap entries; in kNN mode
+// with k <= k_cap at most k - 1, since every kept D is below the k-th
+// smallest), which also holds the histogram and buffers of the radius search;
+// kNN keeps 8 more for the bin of the k-th; at least 2.
+PCMS_HD inline int target_words(int mode, int k, int k_cap)
+{
+    int w = k_cap;
+    if (mode == PCMS_RADIUS_KNN && k + 8 < k_cap) w = k + 8;
+    return w < 2 ? 2 : w;
+}
+
 // Radius and kept list for one target; returns the status bits, the count
 // inside the radius, the number of kept list entries and r^2 (all uniform
 // across the group).
@@ -246,29 +256,21 @@ PCMS_HD PCMS_INLINE int nbr_target(const KArgs &a, const GridParams &gp, int i, 
     return st;
 }
 
-// Loads the coordinates of kept neighbours e0 + j G (j < kNbrBatch) of this
-// lane at once; slots past n repeat neighbour 0 and are flagged invalid.
-template <int D, int G, class S_>
+// Loads the coordinates of kept neighbours e0 + j G (j < B) of this lane at
+// once, with their sorted indices; slots past n repeat neighbour 0 and are
+// flagged invalid.
+template <int D, int G, int B, class S_>
 PCMS_HD PCMS_INLINE void load_neighbours(S_ &S, const double *__restrict__ spts, int e0, int n,
-                                         double (&sb)[kNbrBatch][D], bool (&ok)[kNbrBatch])
-{
-    int pe[kNbrBatch];
-    load_neighbours<D, G>(S, spts, e0, n, sb, ok, pe);
-}
-
-template <int D, int G, class S_>
-PCMS_HD PCMS_INLINE void load_neighbours(S_ &S, const double *__restrict__ spts, int e0, int n,
-                                         double (&sb)[kNbrBatch][D], bool (&ok)[kNbrBatch],
-                                         int (&pe)[kNbrBatch])
+                                         double (&sb)[B][D], bool (&ok)[B], int (&pe)[B])
 {
 #pragma unroll
-    for (int j = 0; j < kNbrBatch; ++j) {
+    for (int j = 0; j < B; ++j) {
         const int e = e0 + j * G;
         ok[j] = e < n;
         pe[j] = S.at(ok[j] ? e : 0);
     }
 #pragma unroll
-    for (int j = 0; j < kNbrBatch; ++j) load_src<D>(spts, pe[j], sb[j]);
+    for (int j = 0; j < B; ++j) load_src<D>(spts, pe[j], sb[j]);
 }
 
 // Per-neighbour local data: monomials p and weight w, in T.
@@ -302,6 +304,9 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
     constexpr int M = Basis<D, P>::M;
     constexpr int MM = Basis<D, P>::MM;
     using TA = typename std::conditional<MIXED, float, double>::type;   // assembly type
+    // neighbours per lane whose loads are issued together, per pass (fewer
+    // where the pass holds more live registers)
+    constexpr int kAsm = MIXED ? 4 : 2, kRef = 2, kApply = 2;
     const int ti = a.tperm[i];
     Search<D, UNIT, G> S{gp, a.cs, a.spts, a.perm, {}, L, a.k_cap, a.words, g};
     load_point<D>(a.tgt, ti, S.t);
@@ -310,41 +315,46 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
     int st = select_target<D, UNIT, G>(S, a, n_found, n, r2);
     if ((st & 0xF) == PCMS_TGT_OK && n < M) st |= PCMS_TGT_UNDERDETERMINED;
     double y[M];
-    double idg[M];
-    double R[MM];
     if ((st & 0xF) == PCMS_TGT_OK) {
         const double inv_h = 1.0 / sqrt(r2);
         const double inv_r2 = 1.0 / r2;
-        // moment matrix G = sum w p p^T (upper triangle); lane q takes the
-        // neighbours e = q, q + G, ... and the group sums the partial moments
-        {
-            TA Gm[MM];
+        // moment matrix G = sum w p p^T (upper triangle, in TA); lane q takes
+        // the neighbours e = q, q + G, ... and the group sums the partials
+        TA Gm[MM];
 #pragma unroll
-            for (int j = 0; j < MM; ++j) Gm[j] = TA(0);
-            for (int e0 = g.q; e0 < n; e0 += G * kNbrBatch) {
-                double sb[kNbrBatch][D];
-                bool ok[kNbrBatch];
-                load_neighbours<D, G>(S, a.spts, e0, n, sb, ok);
+        for (int j = 0; j < MM; ++j) Gm[j] = TA(0);
+        for (int e0 = g.q; e0 < n; e0 += G * kAsm) {
+            double sb[kAsm][D];
+            bool ok[kAsm];
+            int pe[kAsm];
+            load_neighbours<D, G, kAsm>(S, a.spts, e0, n, sb, ok, pe);
 #pragma unroll
-                for (int j = 0; j < kNbrBatch; ++j) {
-                    TA p[M], w;
-                    neighbour_data<D, P, UNIT, TA>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p, w);
-                    w = ok[j] ? w : TA(0);
+            for (int j = 0; j < kAsm; ++j) {
+                TA p[M], w;
+                neighbour_data<D, P, UNIT, TA>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p, w);
+                w = ok[j] ? w : TA(0);
 #pragma unroll
-                    for (int u = 0; u < M; ++u) {
-                        TA wp = w * p[u];
+                for (int u = 0; u < M; ++u) {
+                    TA wp = w * p[u];
 #pragma unroll
-                        for (int v = u; v < M; ++v)
-                            Gm[tri<M>(u, v)] = __builtin_fma(wp, p[v], Gm[tri<M>(u, v)]);
-                    }
+                    for (int v = u; v < M; ++v)
+                        Gm[tri<M>(u, v)] = __builtin_fma(wp, p[v], Gm[tri<M>(u, v)]);
                 }
             }
-#pragma unroll
-            for (int j = 0; j < MM; ++j) R[j] = (double)g.sum(Gm[j]);
         }
 #pragma unroll
-        for (int u = 0; u < M; ++u) R[tri<M>(u, u)] += a.lambda;
-        bool ok = cholesky<M>(R, idg);
+        for (int j = 0; j < MM; ++j) Gm[j] = g.sum(Gm[j]);
+        // FP64 factor of G + lambda I; recomputed (bit-identically) after each
+        // refinement pass rather than kept live across it
+        double R[MM], idg[M];
+        auto factor = [&]() {
+#pragma unroll
+            for (int j = 0; j < MM; ++j) R[j] = (double)Gm[j];
+#pragma unroll
+            for (int u = 0; u < M; ++u) R[tri<M>(u, u)] += a.lambda;
+            return cholesky<M>(R, idg);
+        };
+        bool ok = factor();
 #pragma unroll
         for (int u = 0; u < M; ++u) y[u] = u == 0 ? 1.0 : 0.0;
         chol_solve<M>(R, idg, y);
@@ -358,19 +368,20 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                 double res[M];
 #pragma unroll
                 for (int u = 0; u < M; ++u) res[u] = 0.0;
-                for (int e0 = g.q; e0 < n; e0 += G * kNbrBatch) {
-                    double sb[kNbrBatch][D];
-                    bool ok[kNbrBatch];
-                    load_neighbours<D, G>(S, a.spts, e0, n, sb, ok);
+                for (int e0 = g.q; e0 < n; e0 += G * kRef) {
+                    double sb[kRef][D];
+                    bool okn[kRef];
+                    int pe[kRef];
+                    load_neighbours<D, G, kRef>(S, a.spts, e0, n, sb, okn, pe);
 #pragma unroll
-                    for (int j = 0; j < kNbrBatch; ++j) {
+                    for (int j = 0; j < kRef; ++j) {
                         TA p[M], w;
                         neighbour_data<D, P, UNIT, TA>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p,
                                                        w);
                         double py = 0.0;
 #pragma unroll
                         for (int u = 0; u < M; ++u) py = __builtin_fma((double)p[u], y[u], py);
-                        const double c = ok[j] ? -(double)w * py : 0.0;
+                        const double c = okn[j] ? -(double)w * py : 0.0;
 #pragma unroll
                         for (int u = 0; u < M; ++u) res[u] = __builtin_fma(c, (double)p[u], res[u]);
                     }
@@ -378,6 +389,7 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
 #pragma unroll
                 for (int u = 0; u < M; ++u)
                     res[u] = g.sum(res[u]) + ((u == 0 ? 1.0 : 0.0) - a.lambda * y[u]);
+                factor();
                 chol_solve<M>(R, idg, res);
                 double ny = 0.0, nd = 0.0;
 #pragma unroll
@@ -407,20 +419,20 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                 // centring leaves the fit unchanged only without regularisation
                 fref[l] = (MIXED && a.lambda == 0.0 && l0 + l < a.nf) ? sv0[l0 + l] : 0.0;
             }
-            for (int e0 = g.q; e0 < n; e0 += G * kNbrBatch) {
-                double sb[kNbrBatch][D];
-                bool ok[kNbrBatch];
-                int pe[kNbrBatch];
-                load_neighbours<D, G>(S, a.spts, e0, n, sb, ok, pe);
-                double fv[kNbrBatch][kFieldChunk];
+            for (int e0 = g.q; e0 < n; e0 += G * kApply) {
+                double sb[kApply][D];
+                bool ok[kApply];
+                int pe[kApply];
+                load_neighbours<D, G, kApply>(S, a.spts, e0, n, sb, ok, pe);
+                double fv[kApply][kFieldChunk];
 #pragma unroll
-                for (int j = 0; j < kNbrBatch; ++j) {
+                for (int j = 0; j < kApply; ++j) {
                     const double *sv = a.svals + (size_t)pe[j] * a.nf + l0;
 #pragma unroll
                     for (int l = 0; l < kFieldChunk; ++l) fv[j][l] = (l0 + l < a.nf) ? sv[l] : 0.0;
                 }
 #pragma unroll
-                for (int j = 0; j < kNbrBatch; ++j) {
+                for (int j = 0; j < kApply; ++j) {
                     TA p[M], w;
                     neighbour_data<D, P, UNIT, TA>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p, w);
                     double py = 0.0;

@@ -60,8 +60,11 @@ __global__ void __launch_bounds__(256) k_neighbors(KArgs a)
     add_summary(a.summary, st, active && g.q == 0);
 }
 
+// Three waves per SIMD: the register allocator fits 168 VGPRs (the fit's
+// moment and factor arrays spill a little around the refinement pass), which
+// measured faster than two waves without spills.
 template <int D, int P, bool MIXED, bool UNIT, int G>
-__global__ void __launch_bounds__(256) k_transfer(KArgs a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_transfer(KArgs a)
 {
     extern __shared__ int lds[];
     const int lb = logical_block(a.n_blocks);
@@ -138,18 +141,17 @@ bool unit_metric(const Grid *g)
     return true;
 }
 
-// LDS words of a target: the kept list (k_cap entries), which also serves as
-// a buffer of k_cap / 2 doubles during the radius search (at least one); the
-// per-target stride is odd so neighbouring targets start in different banks.
-int lane_words(int k_cap) { return k_cap < 2 ? 2 : k_cap; }
-int target_stride(int k_cap) { return lane_words(k_cap) | 1; }
+// LDS words of a target (target_words); the per-target stride is odd so
+// neighbouring targets start in different banks.
+int lane_words(const LaunchSpec &ls) { return target_words(ls.radius.mode, ls.radius.k, ls.k_cap); }
+int target_stride(const LaunchSpec &ls) { return lane_words(ls) | 1; }
 
 // Threads per block (kGroup lanes per target); the targets' LDS must fit
 // 64 KiB per workgroup.
-int pick_block(int requested, int k_cap)
+int pick_block(int requested, const LaunchSpec &ls)
 {
     int b = requested > 0 ? requested : 256;
-    while (b > 64 && (size_t)(b / kGroup) * target_stride(k_cap) * sizeof(int) > 65536) b >>= 1;
+    while (b > 64 && (size_t)(b / kGroup) * target_stride(ls) * sizeof(int) > 65536) b >>= 1;
     return b;
 }
 
@@ -171,8 +173,8 @@ KArgs base_args(const LaunchSpec &ls, int block)
     a.k_cap = ls.k_cap;
     const int tpb = block / kGroup;
     a.n_blocks = (int)((ls.n_tgt + tpb - 1) / tpb);
-    a.words = lane_words(ls.k_cap);
-    a.stride = target_stride(ls.k_cap);
+    a.words = lane_words(ls);
+    a.stride = target_stride(ls);
     a.summary = ls.summary;
     return a;
 }
@@ -190,7 +192,7 @@ pcms_status launch_neighbors(const LaunchSpec &ls, int32_t *nbr, int32_t *n_kept
                              int32_t *n_found, double *r2, uint8_t *status, hipStream_t s)
 {
     if (ls.n_tgt == 0) return PCMS_OK;
-    const int block = pick_block(ls.block, ls.k_cap);
+    const int block = pick_block(ls.block, ls);
     KArgs a = base_args(ls, block);
     a.nbr = nbr;
     a.n_kept = n_kept;
@@ -199,7 +201,7 @@ pcms_status launch_neighbors(const LaunchSpec &ls, int32_t *nbr, int32_t *n_kept
     a.status = status;
     KernelFn fn = unit_metric(ls.grid) ? nbr_table<true>(ls.grid->dim) : nbr_table<false>(ls.grid->dim);
     const int launch = ((a.n_blocks + 7) / 8) * 8;
-    const size_t shm = (size_t)(block / kGroup) * target_stride(ls.k_cap) * sizeof(int);
+    const size_t shm = (size_t)(block / kGroup) * target_stride(ls) * sizeof(int);
     hipLaunchKernelGGL(fn, dim3(launch), dim3(block), shm, s, a);
     PCMS_HIP(hipGetLastError());
     return PCMS_OK;
@@ -210,7 +212,7 @@ pcms_status launch_transfer(const LaunchSpec &ls, const double *svals, int n_fie
                             uint8_t *status, hipStream_t s)
 {
     if (ls.n_tgt == 0) return PCMS_OK;
-    const int block = pick_block(ls.block, ls.k_cap);
+    const int block = pick_block(ls.block, ls);
     KArgs a = base_args(ls, block);
     a.svals = svals;
     a.nf = n_fields;
@@ -223,7 +225,7 @@ pcms_status launch_transfer(const LaunchSpec &ls, const double *svals, int n_fie
     KernelFn fn = unit_metric(ls.grid) ? xfer_table<true>(ls.grid->dim, degree, mixed)
                                        : xfer_table<false>(ls.grid->dim, degree, mixed);
     const int launch = ((a.n_blocks + 7) / 8) * 8;
-    const size_t shm = (size_t)(block / kGroup) * target_stride(ls.k_cap) * sizeof(int);
+    const size_t shm = (size_t)(block / kGroup) * target_stride(ls) * sizeof(int);
     hipLaunchKernelGGL(fn, dim3(launch), dim3(block), shm, s, a);
     PCMS_HIP(hipGetLastError());
     return PCMS_OK;

@@ -201,20 +201,6 @@ struct Search {
         unsigned long long hi = (unsigned)at(2 * j + 1);
         return __builtin_bit_cast(double, (hi << 32) | lo);
     }
-    // a double in words w, w + 1 (any w)
-    PCMS_HD PCMS_INLINE void wstore(int w, double v)
-    {
-        unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
-        at(w) = (int)(unsigned)(bits & 0xffffffffull);
-        at(w + 1) = (int)(unsigned)(bits >> 32);
-    }
-    PCMS_HD PCMS_INLINE double wload(int w)
-    {
-        unsigned long long lo = (unsigned)at(w);
-        unsigned long long hi = (unsigned)at(w + 1);
-        return __builtin_bit_cast(double, (hi << 32) | lo);
-    }
-
     template <class F>
     PCMS_HD PCMS_INLINE void each(double rho2, F &&f)
     {
@@ -343,14 +329,22 @@ struct Search {
         return g.min(ans);
     }
 
+    // D of sorted source p
+    PCMS_HD PCMS_INLINE double d2_of(int p) const
+    {
+        double sb[D];
+        load_src<D>(spts, p, sb);
+        return metric_d2<D, UNIT>(t, sb, gp);
+    }
+
     // kNN selection in two walks, for k <= k_cap + 1.  The first walk, over
     // the ball of radius (1 + 0.3) g (g the bucket-count estimate of the
     // radius), counts the sources below lo = ((1 - 0.22) g)^2 and histograms
     // those in [lo, hi = ((1 + 0.3) g)^2) into nb bins of equal width in D
     // (the target's first nb words serve as the bins).  The second walk
     // lists, in walk order, every source of a lower bin (or below lo) and
-    // buffers the (D, index) pairs of the bin holding the k-th at the end of
-    // the words; the k-th is ranked there and the buffered sources below it
+    // keeps the indices of the bin holding the k-th at the end of the words;
+    // the k-th is ranked among them (their D recomputed) and those below it
     // complete the list.  Both walks classify a source with the same
     // expression of its D, so their counts agree exactly.  On success r2 is
     // the k-th smallest D, the list holds every source with D < r2 and
@@ -391,8 +385,9 @@ struct Search {
             }
         }
         g.sync();   // every lane has read the bins before the list overwrites them
-        // the appended entries [c_b, c_b + n_b) must stay below the buffer
-        if (b < 0 || c_b + 4 * n_b > words) return false;
+        if (b < 0 || c_b + n_b > words) return false;
+        // bin entry j sits in word words - n_b + j
+        const int base = words - n_b;
         const double rho2 = b == nb - 1 ? hi : fmin(hi, (lo + (double)(b + 1) * bw) * (1.0 + 1e-12));
         int n = 0, m = 0;
         each(rho2, [&](int p, double d2, bool ok) {
@@ -406,11 +401,7 @@ struct Search {
             }
             if (bb) {
                 const int j = m + g.below(mb);
-                if (j < n_b) {
-                    const int w = words - 3 * (j + 1);
-                    wstore(w, d2);
-                    at(w + 2) = p;
-                }
+                if (j < n_b) at(base + j) = p;
             }
             n += __builtin_popcount(mi);
             m += __builtin_popcount(mb);
@@ -423,10 +414,10 @@ struct Search {
         for (int a0 = 0; a0 < n_b; a0 += G) {
             const int a = a0 + g.q;
             if (a < n_b) {
-                const double v = wload(words - 3 * (a + 1));
+                const double v = d2_of(at(base + a));
                 int less = 0, le = 0;
                 for (int j = 0; j < n_b; ++j) {
-                    const double x = wload(words - 3 * (j + 1));
+                    const double x = d2_of(at(base + j));
                     less += x < v;
                     le += x <= v;
                 }
@@ -434,13 +425,15 @@ struct Search {
             }
         }
         r2 = g.min(ans);
-        // append the bin's sources below r2, in walk order
+        // append the bin's sources below r2 in walk order; entry j is read
+        // before position c_b + j (<= base + j) can be written
         int cnt = c_b;
         for (int j0 = 0; j0 < n_b; j0 += G) {
             const int j = j0 + g.q;
-            const bool take = j < n_b && wload(words - 3 * (min(j, n_b - 1) + 1)) < r2;
-            const int p = take ? at(words - 3 * (j + 1) + 2) : 0;
+            const int p = j < n_b ? at(base + j) : 0;
+            const bool take = j < n_b && d2_of(p) < r2;
             const unsigned mt = g.ballot(take);
+            g.sync();
             if (take) at(cnt + g.below(mt)) = p;
             cnt += __builtin_popcount(mt);
         }

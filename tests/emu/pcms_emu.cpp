@@ -389,7 +389,7 @@ int main(int argc, char **argv)
     a.max_iter = max_iter;
     a.r = r;
     a.k_cap = k_cap;
-    a.words = k_cap < 2 ? 2 : k_cap;
+    a.words = target_words(mode, k, k_cap);
     a.stride = a.words | 1;
     a.svals = svals.data();
     a.nf = (int)nf;
