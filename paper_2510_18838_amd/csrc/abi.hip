@@ -336,7 +336,7 @@ static pcms_status transfer_common(const Grid *g, const double *src_vals, int32_
     sc.s = s;
     size_t off_tperm = 64;
     size_t off_svals = off_tperm + ((sizeof(int) * (size_t)n_tgt + 255) & ~(size_t)255);
-    size_t bytes = off_svals + sizeof(double) * (size_t)g->n_src * n_fields;
+    size_t bytes = off_svals + sizeof(double) * (size_t)g->n_src * padded_dim(n_fields);
     pcms_status st = scratch_alloc(&sc.p, bytes, s);
     if (st != PCMS_OK) return st;
     int32_t *summary = async ? o.summary : (int32_t *)sc.p;

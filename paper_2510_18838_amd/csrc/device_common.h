@@ -219,6 +219,19 @@ PCMS_HD PCMS_INLINE void load_src(const double *__restrict__ spts, int p, double
 #endif
 }
 
+// Two consecutive doubles from a 16-byte aligned address, in one load.
+PCMS_HD PCMS_INLINE void load_pair(const double *__restrict__ p, double &x, double &y)
+{
+#ifdef PCMS_HOST_EMULATION
+    x = p[0];
+    y = p[1];
+#else
+    const double2 v = *reinterpret_cast<const double2 *>(p);
+    x = v.x;
+    y = v.y;
+#endif
+}
+
 // Atomic add to a word of the block's LDS.
 PCMS_HD PCMS_INLINE void lds_add(int *w, int v)
 {

@@ -158,8 +158,9 @@ struct KArgs {
     int stride;            // LDS words between consecutive targets of a block (odd)
     int n_blocks;          // logical blocks (before XCD padding)
     // transfer only
-    const double *svals;   // [n_src][nf], sorted order
+    const double *svals;   // [n_src][nfs], sorted order, zero padded
     int nf;
+    int nfs;               // padded_dim(nf): 16-byte aligned value records
     int weight;
     int refine;
     double lambda;
@@ -410,7 +411,7 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
     if ((st & 0xF) == PCMS_TGT_OK) {
         const double inv_h = 1.0 / sqrt(r2);
         const double inv_r2 = 1.0 / r2;
-        const double *sv0 = a.svals + (size_t)S.at(0) * a.nf;
+        const double *sv0 = a.svals + (size_t)S.at(0) * a.nfs;
         for (int l0 = 0; l0 < a.nf; l0 += kFieldChunk) {
             double acc[kFieldChunk], fref[kFieldChunk];
 #pragma unroll
@@ -427,9 +428,12 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                 double fv[kApply][kFieldChunk];
 #pragma unroll
                 for (int j = 0; j < kApply; ++j) {
-                    const double *sv = a.svals + (size_t)pe[j] * a.nf + l0;
+                    const double *sv = a.svals + (size_t)pe[j] * a.nfs + l0;
 #pragma unroll
-                    for (int l = 0; l < kFieldChunk; ++l) fv[j][l] = (l0 + l < a.nf) ? sv[l] : 0.0;
+                    for (int h = 0; h < kFieldChunk / 2; ++h) {
+                        fv[j][2 * h] = fv[j][2 * h + 1] = 0.0;
+                        if (l0 + 2 * h < a.nfs) load_pair(sv + 2 * h, fv[j][2 * h], fv[j][2 * h + 1]);
+                    }
                 }
 #pragma unroll
                 for (int j = 0; j < kApply; ++j) {

@@ -367,13 +367,17 @@ __global__ void k_gather_pts(const double *__restrict__ src, const int *__restri
 
 // Fields into bucket order, [n][nf]: read each field coalesced in source
 // order, write the whole row of a source at its sorted slot.
+// Field values of source j to its sorted slot as one record of padded_dim(nf)
+// doubles (the padding written as zero).
 __global__ void k_scatter_vals(const double *__restrict__ vals, const int *__restrict__ iperm,
                                int64_t n, int nf, double *__restrict__ svals)
 {
+    const int nfs = padded_dim(nf);
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * blockDim.x) {
-        double *row = svals + (int64_t)iperm[j] * nf;
+        double *row = svals + (int64_t)iperm[j] * nfs;
         for (int l = 0; l < nf; ++l) row[l] = vals[(int64_t)l * n + j];
+        if (nfs > nf) row[nf] = 0.0;
     }
 }
 

@@ -216,6 +216,7 @@ pcms_status launch_transfer(const LaunchSpec &ls, const double *svals, int n_fie
     KArgs a = base_args(ls, block);
     a.svals = svals;
     a.nf = n_fields;
+    a.nfs = padded_dim(n_fields);
     a.weight = weight;
     a.refine = precision == PCMS_MIXED_REFINE;
     a.lambda = lambda;

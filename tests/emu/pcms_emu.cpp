@@ -371,9 +371,10 @@ int main(int argc, char **argv)
         while (tbits < 32 && (double)(1ull << tbits) < bound) ++tbits;
     }
     radix_sort_emu(tkeys, tperm, tbits);
-    std::vector<double> svals((size_t)(n_src * nf));
+    const int nfs = padded_dim((int)nf);
+    std::vector<double> svals((size_t)(n_src * nfs), 0.0);
     for (int64_t p = 0; p < n_src; ++p)
-        for (int l = 0; l < nf; ++l) svals[p * nf + l] = vals[(size_t)l * n_src + perm[p]];
+        for (int l = 0; l < nf; ++l) svals[p * nfs + l] = vals[(size_t)l * n_src + perm[p]];
 
     KArgs a{};
     a.gp = &gp;
@@ -393,6 +394,7 @@ int main(int argc, char **argv)
     a.stride = a.words | 1;
     a.svals = svals.data();
     a.nf = (int)nf;
+    a.nfs = nfs;
     a.weight = weight;
     a.refine = precision == PCMS_MIXED_REFINE;
     a.lambda = lambda;
