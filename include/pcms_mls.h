@@ -115,7 +115,7 @@ typedef struct {
     int32_t precision;        /* PCMS_FP64 / PCMS_MIXED / PCMS_MIXED_REFINE */
     double lambda;            /* Tikhonov parameter of Eq. 1, >= 0, in the radius-scaled basis */
     uint32_t flags;           /* PCMS_ASYNC | PCMS_PROFILE */
-    int32_t block;            /* threads per workgroup (4 per target): 0 = library choice, else 64/128/256 */
+    int32_t block;            /* threads per workgroup (one per target): 0 = library choice, else 64/128/256 */
     int32_t *summary;         /* device int32[4] or NULL: counts of statuses 1, 2, 3 and CAPPED */
 } pcms_mls_opts;
 
@@ -168,6 +168,94 @@ pcms_status pcms_mls_transfer_grid(const pcms_grid *grid, const double *src_vals
                                    const pcms_radius *radius, int32_t k_cap,
                                    const pcms_mls_opts *opts, pcms_stream_t stream,
                                    double *tgt_vals, uint8_t *status);
+
+/* ---------------------------------------------------------------------- */
+/* Batched transfer: many independent problems of uneven size, dimension,  */
+/* degree and field count (each one the operation of pcms_mls_transfer)    */
+/* executed by one persistent kernel from a work queue, with every stage   */
+/* captured once into a HIP graph and replayed.                            */
+/* ---------------------------------------------------------------------- */
+
+/* One problem of a batch.  Every pointer is a DEVICE pointer except
+ * inv_scale (HOST float64[dim] or NULL), and must stay valid, at the same
+ * address, for the life of the plan: a plan replays against these buffers,
+ * so new source values written into src_vals between executions are picked
+ * up.  Constraints as for pcms_mls_transfer; status may be NULL. */
+typedef struct {
+    const double *src;        /* [n_src][dim] */
+    int64_t n_src;
+    int32_t dim;              /* 1..5 */
+    int32_t basis_degree;     /* 0..2 */
+    const double *src_vals;   /* [n_fields][n_src] */
+    int32_t n_fields;         /* >= 1 */
+    int32_t k_cap;            /* m..256 */
+    const double *tgt;        /* [n_tgt][dim] */
+    int64_t n_tgt;            /* >= 0 */
+    pcms_radius radius;
+    const double *inv_scale;  /* HOST [dim] or NULL */
+    double *tgt_vals;         /* [n_fields][n_tgt] */
+    uint8_t *status;          /* [n_tgt] or NULL */
+} pcms_problem;
+
+/* Batch options.  block (targets per workgroup) and cell_factor (bucket
+ * width as a fraction of the radius: of the fixed or initial radius, or of
+ * the expected kNN radius) are tuning knobs that change speed, not results;
+ * 0 takes the value stored in tune_cache (a file written by pcms_autotune)
+ * if given and readable, else the library default. */
+typedef struct {
+    int32_t weight;           /* PCMS_WEIGHT_* (all problems) */
+    int32_t precision;        /* PCMS_FP64 / PCMS_MIXED / PCMS_MIXED_REFINE */
+    double lambda;            /* >= 0 */
+    int32_t block;            /* 0, 64, 128 or 256 */
+    double cell_factor;       /* 0 or in (0, 4] */
+    const char *tune_cache;   /* HOST path or NULL */
+} pcms_batch_opts;
+
+/* Set opts to the defaults (Wendland C2, MIXED_REFINE, lambda 0, library
+ * tuning). */
+void pcms_batch_opts_default(pcms_batch_opts *opts);
+
+typedef struct pcms_batch_plan pcms_batch_plan;
+
+/* Plan a batch of n >= 1 problems: validates every problem (an invalid one
+ * fails the call with its index in the message), allocates the device
+ * workspace of all grids, sorted copies and the work queue (library owned,
+ * released by pcms_batch_plan_free), and orders the work items (problem,
+ * tile of targets) by estimated cost, largest first.  Nothing is enqueued;
+ * the work is captured on the first pcms_batch_plan_exec. */
+pcms_status pcms_batch_plan_create(const pcms_problem *problems, int32_t n,
+                                   const pcms_batch_opts *opts, pcms_batch_plan **out);
+
+/* Execute the plan on `stream`: every grid build, target ordering and
+ * value scatter, then one persistent launch that takes (problem, tile)
+ * items from an atomic counter until the queue is empty (problems of
+ * dimension 4 or 5 run through the one-problem kernel after it).  The first
+ * call on a plan with a non-null stream captures the sequence into a HIP
+ * graph and later calls replay it (the legacy null stream cannot be
+ * captured: there every call enqueues the kernels directly).  summary: DEVICE int32[4] or NULL.  With summary NULL the call waits
+ * and returns the batch's status code as pcms_mls_transfer does; with a
+ * summary it returns after enqueue and the counts of statuses 1, 2, 3 and
+ * CAPPED over all problems land there.  Calls on one plan must not overlap. */
+pcms_status pcms_batch_plan_exec(pcms_batch_plan *plan, pcms_stream_t stream, int32_t *summary);
+
+/* Release the plan's workspace and graph (waits for the device first). */
+pcms_status pcms_batch_plan_free(pcms_batch_plan *plan);
+
+/* Tuning knobs chosen by pcms_autotune. */
+typedef struct {
+    int32_t block;
+    double cell_factor;
+    float ms;                 /* measured time of one execution */
+} pcms_tune_result;
+
+/* Time executions of the batch `sample` for each (block, cell_factor) in
+ * {64, 128, 256} x {0.6, 0.7, 0.85, 1.0} (weight, precision and lambda from
+ * opts) and return the fastest in *out; when cache_path is not NULL it is
+ * also written there as a small JSON object that pcms_batch_plan_create
+ * reads through pcms_batch_opts.tune_cache.  Runs on `stream` and
+ * synchronises it. */
+pcms_status pcms_autotune(const pcms_problem *sample, int32_t n, const pcms_batch_opts *opts,
+                          const char *cache_path, pcms_stream_t stream, pcms_tune_result *out);
 
 /* Phase times in milliseconds of the calling thread's last call made with
  * PCMS_PROFILE, measured with HIP events on that call's stream: [0] grid

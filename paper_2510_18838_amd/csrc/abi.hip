@@ -6,11 +6,14 @@
 #include <stdlib.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
 
+#include "fit.h"
 #include "internal.h"
 
 namespace pcms {
@@ -79,17 +82,40 @@ pcms_status check_opts(const pcms_mls_opts *o)
 // Cell sizing for a one-shot call: buckets a fixed fraction of the support
 // radius wide (0.7 of the expected kNN radius, one fixed or initial radius);
 // PCMS_CELL_FACTOR overrides the fraction.
-void cell_spec(const pcms_radius *r, int dim, double *cell_width, double *pts_per_cell)
+void cell_spec(const pcms_radius *r, int dim, double *cell_width, double *pts_per_cell,
+               double cf_override = 0.0)
 {
     *cell_width = 0.0;
     *pts_per_cell = 0.0;
     const char *env = getenv("PCMS_CELL_FACTOR");
-    double cf = env ? atof(env) : (r->mode == PCMS_RADIUS_KNN ? 0.7 : 1.0);
+    double cf = cf_override > 0.0 ? cf_override
+              : env ? atof(env) : (r->mode == PCMS_RADIUS_KNN ? 0.7 : 1.0);
     if (!(cf > 0.0)) cf = 1.0;
     if (r->mode == PCMS_RADIUS_KNN)
         *pts_per_cell = pow(cf, dim) * r->k / unit_ball_volume(dim);
     else
         *cell_width = cf * r->r;
+}
+
+// Reads {"block": B, "cell_factor": F} from a file written by pcms_autotune.
+bool read_tune_cache(const char *path, int *block, double *cf)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char buf[512];
+    const size_t n = std::fread(buf, 1, sizeof(buf) - 1, f);
+    std::fclose(f);
+    buf[n] = 0;
+    const char *b = std::strstr(buf, "\"block\":");
+    const char *c = std::strstr(buf, "\"cell_factor\":");
+    if (!b || !c) return false;
+    const int bv = std::atoi(b + 8);
+    const double cv = std::atof(c + 14);
+    if (bv != 64 && bv != 128 && bv != 256) return false;
+    if (!(cv > 0.0 && cv <= 4.0)) return false;
+    *block = bv;
+    *cf = cv;
+    return true;
 }
 
 struct Scratch {
@@ -433,6 +459,203 @@ pcms_status pcms_mls_transfer_grid(const pcms_grid *grid, const double *src_vals
     if ((st = g_prof.mark(1)) != PCMS_OK) return st;   // no grid build in this call
     return transfer_common(g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts,
                            (hipStream_t)stream, tgt_vals, status);
+}
+
+void pcms_batch_opts_default(pcms_batch_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->weight = PCMS_WEIGHT_WENDLAND_C2;
+    o->precision = PCMS_MIXED_REFINE;
+}
+
+pcms_status pcms_batch_plan_create(const pcms_problem *problems, int32_t n,
+                                   const pcms_batch_opts *opts, pcms_batch_plan **out)
+{
+    if (!out) return arg_error("out is NULL");
+    *out = nullptr;
+    if (n < 1 || !problems) return arg_error("a batch needs n >= 1 problems");
+    pcms_batch_opts o;
+    pcms_batch_opts_default(&o);
+    if (opts) o = *opts;
+    pcms_mls_opts mo;
+    pcms_mls_opts_default(&mo);
+    mo.weight = o.weight;
+    mo.precision = o.precision;
+    mo.lambda = o.lambda;
+    pcms_status st = check_opts(&mo);
+    if (st != PCMS_OK) return st;
+    if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
+        return arg_error("block must be 0, 64, 128 or 256");
+    if (!(o.cell_factor >= 0.0 && o.cell_factor <= 4.0)) return arg_error("cell_factor must be 0 or in (0, 4]");
+    int block = o.block;
+    double cf = o.cell_factor;
+    if ((block == 0 || cf == 0.0) && o.tune_cache) {
+        int tb = 0;
+        double tcf = 0.0;
+        if (read_tune_cache(o.tune_cache, &tb, &tcf)) {
+            if (block == 0) block = tb;
+            if (cf == 0.0) cf = tcf;
+        }
+    }
+    if (block == 0) block = 256;
+    std::unique_ptr<BatchPlan> p(new (std::nothrow) BatchPlan());
+    if (!p) return PCMS_ERR_NOMEM;
+    p->n = n;
+    p->weight = o.weight;
+    p->precision = o.precision;
+    p->lambda = o.lambda;
+    p->block = block;
+    p->cell_factor = cf;
+    p->hp.assign(n, BatchProb{});
+    for (int q = 0; q < n; ++q) {
+        const pcms_problem &P = problems[q];
+        const std::string at = "problem " + std::to_string(q) + ": ";
+        if (P.n_src < 1 || P.n_src >= ((int64_t)1 << 31) / 2) return arg_error(at + "n_src must be in [1, 2^30)");
+        if (!P.src) return arg_error(at + "src is NULL");
+        st = check_transfer_args(P.n_src, P.dim, P.src_vals, P.n_fields, P.tgt, P.n_tgt, P.basis_degree,
+                                 &P.radius, P.k_cap, &mo, P.tgt_vals);
+        if (st != PCMS_OK) return arg_error(at + pcms_last_error());
+        if ((st = check_scale(P.inv_scale, P.dim)) != PCMS_OK) return arg_error(at + pcms_last_error());
+        BatchProb &B = p->hp[q];
+        B.src = P.src;
+        B.vals = P.src_vals;
+        B.tgt = P.tgt;
+        B.out = P.tgt_vals;
+        B.status = P.status;
+        B.n_src = (int)P.n_src;
+        B.n_tgt = (int)P.n_tgt;
+        B.dim = P.dim;
+        B.degree = P.basis_degree;
+        B.nf = P.n_fields;
+        B.nfs = padded_dim(P.n_fields);
+        B.k_cap = P.k_cap;
+        B.words = target_words(P.radius.mode, P.radius.k, P.k_cap);
+        B.stride = B.words | 1;
+        B.mode = P.radius.mode;
+        B.k = P.radius.k;
+        B.n_min = P.radius.n_min;
+        B.max_iter = P.radius.max_iter;
+        B.r = P.radius.r;
+        B.cells_cap = cells_cap_for(P.n_src);
+        B.unit = 1;
+        for (int k = 0; k < kMaxDim; ++k) {
+            B.g[k] = (P.inv_scale && k < P.dim) ? P.inv_scale[k] : 1.0;
+            if (B.g[k] != 1.0) B.unit = 0;
+        }
+        cell_spec(&P.radius, P.dim, &B.cell_width, &B.pts_per_cell, cf);
+    }
+    // the per-target LDS of one block must fit a workgroup
+    int max_stride = 1;
+    for (const BatchProb &B : p->hp) max_stride = std::max(max_stride, B.stride);
+    while (p->block > 64 && (size_t)p->block * max_stride * sizeof(int) > 65536) p->block >>= 1;
+    if ((st = batch_setup(*p)) != PCMS_OK) return st;
+    *out = reinterpret_cast<pcms_batch_plan *>(p.release());
+    return PCMS_OK;
+}
+
+pcms_status pcms_batch_plan_exec(pcms_batch_plan *plan, pcms_stream_t stream, int32_t *summary)
+{
+    if (!plan) return arg_error("plan is NULL");
+    BatchPlan &p = *reinterpret_cast<BatchPlan *>(plan);
+    hipStream_t s = (hipStream_t)stream;
+    pcms_status st;
+    if (!s) {
+        // the legacy null stream cannot be captured: plain enqueue
+        if ((st = batch_enqueue(p, s)) != PCMS_OK) return st;
+    } else {
+        if (!p.exec) {
+            PCMS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            st = batch_enqueue(p, s);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(s, &g);
+            if (st != PCMS_OK) {
+                if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            PCMS_HIP(e);
+            e = hipGraphInstantiate(&p.exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                p.exec = nullptr;
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            p.graph = g;
+        }
+        PCMS_HIP(hipGraphLaunch(p.exec, s));
+    }
+    if (summary) return batch_copy_summary(p.summary, summary, s);
+    return finish(p.summary, false, s, true);
+}
+
+pcms_status pcms_batch_plan_free(pcms_batch_plan *plan)
+{
+    if (!plan) return PCMS_OK;
+    BatchPlan *p = reinterpret_cast<BatchPlan *>(plan);
+    (void)hipDeviceSynchronize();
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->ws) (void)hipFree(p->ws);
+    delete p;
+    return PCMS_OK;
+}
+
+pcms_status pcms_autotune(const pcms_problem *sample, int32_t n, const pcms_batch_opts *opts,
+                          const char *cache_path, pcms_stream_t stream, pcms_tune_result *out)
+{
+    if (!out) return arg_error("out is NULL");
+    pcms_batch_opts o;
+    pcms_batch_opts_default(&o);
+    if (opts) o = *opts;
+    o.tune_cache = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PCMS_HIP(hipEventCreate(&e0));
+    PCMS_HIP(hipEventCreate(&e1));
+    const int blocks[3] = {64, 128, 256};
+    const double cfs[4] = {0.6, 0.7, 0.85, 1.0};
+    pcms_tune_result best{0, 0.0, INFINITY};
+    pcms_status st = PCMS_OK;
+    int32_t *sum = nullptr;
+    hipError_t he = hipMalloc(&sum, sizeof(int32_t) * 4);
+    if (he != hipSuccess) st = hip_fail(he, "hipMalloc(summary)");
+    for (int bi = 0; bi < 3 && st == PCMS_OK; ++bi) {
+        for (int ci = 0; ci < 4 && st == PCMS_OK; ++ci) {
+            o.block = blocks[bi];
+            o.cell_factor = cfs[ci];
+            pcms_batch_plan *plan = nullptr;
+            if ((st = pcms_batch_plan_create(sample, n, &o, &plan)) != PCMS_OK) break;
+            // first execution captures the graph; then three timed replays
+            st = pcms_batch_plan_exec(plan, stream, sum);
+            float ms = 0.0f;
+            if (st == PCMS_OK && hipEventRecord(e0, s) == hipSuccess) {
+                for (int r = 0; r < 3 && st == PCMS_OK; ++r) st = pcms_batch_plan_exec(plan, stream, sum);
+                if (st == PCMS_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                                      hipEventSynchronize(e1) != hipSuccess ||
+                                      hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    st = hip_fail(hipGetLastError(), "autotune timing");
+            }
+            pcms_batch_plan_free(plan);
+            ms /= 3.0f;
+            if (st == PCMS_OK && ms < best.ms) best = pcms_tune_result{blocks[bi], cfs[ci], ms};
+        }
+    }
+    if (sum) (void)hipFree(sum);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != PCMS_OK) return st;
+    *out = best;
+    if (cache_path) {
+        FILE *f = std::fopen(cache_path, "w");
+        if (!f) {
+            set_error(std::string("cannot write ") + cache_path);
+            return PCMS_ERR_ARG;
+        }
+        std::fprintf(f, "{\"block\": %d, \"cell_factor\": %.17g, \"ms\": %.6g}\n", best.block,
+                     best.cell_factor, (double)best.ms);
+        std::fclose(f);
+    }
+    return PCMS_OK;
 }
 
 }  // extern "C"

@@ -487,6 +487,23 @@ pcms_status sort_targets(const Grid *grid, const double *tgt, int64_t n_tgt, int
     return PCMS_OK;
 }
 
+pcms_status sort_pairs(unsigned *k0, int *v0, unsigned *k1, int *v1, int n, int bits, int *hist,
+                       int *scan_scratch, hipStream_t s)
+{
+    return radix_sort(k0, v0, k1, v1, n, bits, hist, scan_scratch, s);
+}
+
+size_t sort_hist_ints(int n) { return (size_t)256 * ((n + kSortItems - 1) / kSortItems); }
+
+size_t sort_scan_ints(int n) { return (size_t)scan_scratch_ints((int)sort_hist_ints(n)); }
+
+int bits_for(double bound)
+{
+    int b = 0;
+    while (b < 32 && (double)(1ull << b) < bound) ++b;
+    return b;
+}
+
 pcms_status gather_values(const Grid *grid, const double *vals, int n_fields, double *svals,
                           hipStream_t s)
 {

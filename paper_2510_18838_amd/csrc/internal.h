@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "device_common.h"
 #include "pcms_mls.h"
@@ -52,6 +53,16 @@ pcms_status sort_targets(const Grid *grid, const double *tgt, int64_t n_tgt, int
 pcms_status gather_values(const Grid *grid, const double *vals, int n_fields, double *svals,
                           hipStream_t s);
 
+// Stable LSD radix sort of (key, value) pairs by the low `bits` key bits; the
+// result ends in (k0, v0).  hist and scan_scratch hold sort_hist_ints(n) and
+// sort_scan_ints(n) ints.  Enqueues kernels and device copies only.
+pcms_status sort_pairs(unsigned *k0, int *v0, unsigned *k1, int *v1, int n, int bits, int *hist,
+                       int *scan_scratch, hipStream_t s);
+size_t sort_hist_ints(int n);
+size_t sort_scan_ints(int n);
+// Smallest b <= 32 with 2^b >= bound.
+int bits_for(double bound);
+
 // search and fit (mls.hip) ----------------------------------------------------
 struct LaunchSpec {
     const Grid *grid;
@@ -72,5 +83,64 @@ pcms_status launch_transfer(const LaunchSpec &ls, const double *svals, int n_fie
                             uint8_t *status, hipStream_t s);
 
 pcms_status zero_ints(int32_t *p, int n, hipStream_t s);
+
+// batched transfer (batch.hip) -------------------------------------------------
+// Device descriptor of one problem of a batch; its grid, sorted copies and
+// target order are slices of the batch's global arrays at the given offsets.
+struct BatchProb {
+    const double *src;
+    const double *vals;
+    const double *tgt;
+    double *out;
+    uint8_t *status;
+    int64_t src_off;      // into the global source order (perm, iperm, keys)
+    int64_t tgt_off;      // into the global target order (tperm)
+    int64_t cs_off;       // into the global cell_start array
+    int64_t spts_off;     // doubles, into the sorted coordinates
+    int64_t sval_off;     // doubles, into the sorted field records
+    unsigned key_off;     // source sort keys: key_off + bucket id
+    unsigned tkey_off;    // target sort keys: tkey_off + processing-order key
+    int n_src, n_tgt, dim, degree, nf, nfs, k_cap, words, stride;
+    int mode, k, n_min, max_iter, unit, tiled, cells_cap;
+    double r, cell_width, pts_per_cell;
+    double g[kMaxDim];
+};
+
+// A planned batch: host descriptors and the device workspace (one
+// allocation) of every stage.
+struct BatchPlan {
+    int n = 0;
+    std::vector<BatchProb> hp;
+    int weight = 0, precision = 0, block = 256;
+    double lambda = 0.0, cell_factor = 0.0;
+    int64_t n_src_tot = 0, n_tgt_tot = 0, cs_tot = 0;
+    int key_bits = 0, tkey_bits = 0, max_stride = 1;
+    void *ws = nullptr;
+    BatchProb *probs_d = nullptr;
+    GridParams *params = nullptr;
+    long long *bb = nullptr;          // [n][2][kMaxDim] ordered min/max keys
+    int64_t *src_pref = nullptr, *tgt_pref = nullptr, *cs_pref = nullptr;   // [n + 1]
+    unsigned *k0 = nullptr, *k1 = nullptr;
+    int *v0 = nullptr, *v1 = nullptr, *hist = nullptr, *scan = nullptr;
+    int *cs = nullptr, *perm = nullptr, *iperm = nullptr, *tperm = nullptr;
+    double *spts = nullptr, *svals = nullptr;
+    int4 *items = nullptr;
+    int n_items = 0;
+    int *counter = nullptr;
+    int32_t *summary = nullptr;       // device [4]
+    int persist_blocks = 0;
+    std::vector<int> outer;           // problems of dimension > 3: one-problem kernel
+    std::vector<Grid> views;          // host views of every problem's grid slices
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+// Lays out the workspace of a plan whose hp[] sizes are filled in (sets the
+// offsets, the work items and the device pointers); allocates it.
+pcms_status batch_setup(BatchPlan &p);
+// Enqueues every stage of the plan on s (no allocation, no host sync).
+pcms_status batch_enqueue(BatchPlan &p, hipStream_t s);
+// Copies the 4 status counts (device to device, enqueued on s).
+pcms_status batch_copy_summary(const int32_t *from, int32_t *to, hipStream_t s);
 
 }  // namespace pcms

@@ -1,0 +1,36 @@
+// Device helpers shared by the kernels of the one-problem and batched
+// transfer launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pcms_mls.h"
+
+namespace pcms {
+
+// Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// range of (spatially sorted) target blocks so its L2 sees neighbouring work.
+__device__ __forceinline__ int logical_block(int n_blocks)
+{
+    const int per = (n_blocks + 7) >> 3;
+    return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+}
+
+// Adds the wave's counts of statuses 1, 2, 3 and CAPPED to summary[0..3]
+// (one atomic per wave and count).
+__device__ __forceinline__ void add_summary(int32_t *summary, int st, bool active)
+{
+    if (!summary) return;
+    unsigned long long b1 = __ballot(active && (st & 0xF) == PCMS_TGT_UNDERDETERMINED);
+    unsigned long long b2 = __ballot(active && (st & 0xF) == PCMS_TGT_SINGULAR);
+    unsigned long long b3 = __ballot(active && (st & 0xF) == PCMS_TGT_RADIUS_EXHAUSTED);
+    unsigned long long b4 = __ballot(active && (st & PCMS_TGT_CAPPED));
+    if ((threadIdx.x & 63) == 0) {
+        if (b1) atomicAdd(&summary[0], (int)__popcll(b1));
+        if (b2) atomicAdd(&summary[1], (int)__popcll(b2));
+        if (b3) atomicAdd(&summary[2], (int)__popcll(b3));
+        if (b4) atomicAdd(&summary[3], (int)__popcll(b4));
+    }
+}
+
+}  // namespace pcms

@@ -7,33 +7,11 @@
 
 #include "fit.h"
 #include "internal.h"
+#include "launch_common.h"
 
 namespace pcms {
 
 namespace {
-
-// Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
-// range of (spatially sorted) target blocks so its L2 sees neighbouring work.
-__device__ __forceinline__ int logical_block(int n_blocks)
-{
-    const int per = (n_blocks + 7) >> 3;
-    return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-}
-
-__device__ __forceinline__ void add_summary(int32_t *summary, int st, bool active)
-{
-    if (!summary) return;
-    unsigned long long b1 = __ballot(active && (st & 0xF) == PCMS_TGT_UNDERDETERMINED);
-    unsigned long long b2 = __ballot(active && (st & 0xF) == PCMS_TGT_SINGULAR);
-    unsigned long long b3 = __ballot(active && (st & 0xF) == PCMS_TGT_RADIUS_EXHAUSTED);
-    unsigned long long b4 = __ballot(active && (st & PCMS_TGT_CAPPED));
-    if ((threadIdx.x & 63) == 0) {
-        if (b1) atomicAdd(&summary[0], (int)__popcll(b1));
-        if (b2) atomicAdd(&summary[1], (int)__popcll(b2));
-        if (b3) atomicAdd(&summary[2], (int)__popcll(b3));
-        if (b4) atomicAdd(&summary[3], (int)__popcll(b4));
-    }
-}
 
 // Lanes per target (G consecutive lanes of a wave); the block's targets are
 // consecutive in processing order and each owns `stride` LDS words.

@@ -34,7 +34,8 @@ PROFILE = 0x2
 
 EXPORTED = ("pcms_mls_opts_default", "pcms_grid_build", "pcms_grid_free", "pcms_neighbors",
             "pcms_mls_transfer", "pcms_mls_transfer_grid", "pcms_last_phase_ms", "pcms_version",
-            "pcms_last_error")
+            "pcms_last_error", "pcms_batch_opts_default", "pcms_batch_plan_create",
+            "pcms_batch_plan_exec", "pcms_batch_plan_free", "pcms_autotune")
 
 
 class PcmsError(RuntimeError):
@@ -52,6 +53,25 @@ class MlsOpts(ctypes.Structure):
     _fields_ = [("weight", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("lam", ctypes.c_double), ("flags", ctypes.c_uint32), ("block", ctypes.c_int32),
                 ("summary", ctypes.c_void_p)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("n_src", ctypes.c_int64), ("dim", ctypes.c_int32),
+                ("basis_degree", ctypes.c_int32), ("src_vals", ctypes.c_void_p),
+                ("n_fields", ctypes.c_int32), ("k_cap", ctypes.c_int32), ("tgt", ctypes.c_void_p),
+                ("n_tgt", ctypes.c_int64), ("radius", Radius), ("inv_scale", ctypes.c_void_p),
+                ("tgt_vals", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("weight", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("lam", ctypes.c_double), ("block", ctypes.c_int32),
+                ("cell_factor", ctypes.c_double), ("tune_cache", ctypes.c_char_p)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("cell_factor", ctypes.c_double),
+                ("ms", ctypes.c_float)]
 
 
 _lib = None
@@ -88,6 +108,18 @@ def lib() -> ctypes.CDLL:
     L.pcms_version.restype = i32
     L.pcms_last_error.argtypes = []
     L.pcms_last_error.restype = ctypes.c_char_p
+    L.pcms_batch_opts_default.argtypes = [ctypes.POINTER(BatchOpts)]
+    L.pcms_batch_opts_default.restype = None
+    L.pcms_batch_plan_create.argtypes = [ctypes.POINTER(Problem), i32, ctypes.POINTER(BatchOpts),
+                                         ctypes.POINTER(P)]
+    L.pcms_batch_plan_create.restype = i32
+    L.pcms_batch_plan_exec.argtypes = [P, P, P]
+    L.pcms_batch_plan_exec.restype = i32
+    L.pcms_batch_plan_free.argtypes = [P]
+    L.pcms_batch_plan_free.restype = i32
+    L.pcms_autotune.argtypes = [ctypes.POINTER(Problem), i32, ctypes.POINTER(BatchOpts),
+                                ctypes.c_char_p, P, ctypes.POINTER(TuneResult)]
+    L.pcms_autotune.restype = i32
     _lib = L
     return L
 
@@ -254,3 +286,101 @@ def pcms_mls_transfer_grid(grid: Grid, src_vals: torch.Tensor, tgt: torch.Tensor
 def radius_of(prob) -> Radius:
     """Radius spec of a synth.Problem."""
     return radius(prob.mode, prob.radius, prob.k, prob.n_min, prob.max_iter)
+
+
+# --- batched transfer ------------------------------------------------------
+
+def batch_opts(weight=WEIGHT_WENDLAND_C2, precision=MIXED_REFINE, lam=0.0, block=0,
+               cell_factor=0.0, tune_cache: Optional[str] = None) -> BatchOpts:
+    o = BatchOpts()
+    lib().pcms_batch_opts_default(ctypes.byref(o))
+    o.weight, o.precision, o.lam, o.block, o.cell_factor = weight, precision, lam, block, cell_factor
+    o.tune_cache = None if tune_cache is None else tune_cache.encode()
+    return o
+
+
+class BatchProblem:
+    """Device tensors of one problem of a batch (kept alive by the plan)."""
+
+    def __init__(self, src, src_vals, tgt, basis_degree, rad: Radius, k_cap, inv_scale=None,
+                 out=None, status=None):
+        _dev(src, torch.float64, "src")
+        _dev(tgt, torch.float64, "tgt")
+        self.src, self.tgt = src, tgt
+        self.src_vals = _dev(src_vals if src_vals.dim() == 2 else src_vals.view(1, -1),
+                             torch.float64, "src_vals")
+        nf, n_tgt = self.src_vals.shape[0], tgt.shape[0]
+        self.out = out if out is not None else torch.empty((nf, n_tgt), dtype=torch.float64,
+                                                           device=tgt.device)
+        self.status = status if status is not None else torch.empty(n_tgt, dtype=torch.uint8,
+                                                                    device=tgt.device)
+        self.basis_degree, self.rad, self.k_cap = int(basis_degree), rad, int(k_cap)
+        self.inv_scale = inv_scale
+
+    def c_struct(self):
+        n_src, dim = self.src.shape
+        keep, g = _host_scale(self.inv_scale, dim)
+        p = Problem(self.src.data_ptr(), n_src, dim, self.basis_degree, self.src_vals.data_ptr(),
+                    self.src_vals.shape[0], self.k_cap, self.tgt.data_ptr(), self.tgt.shape[0],
+                    self.rad, None if g is None else g.value, self.out.data_ptr(),
+                    self.status.data_ptr())
+        return p, keep
+
+
+def _problem_array(problems):
+    arr = (Problem * len(problems))()
+    keep = []
+    for i, bp in enumerate(problems):
+        arr[i], k = bp.c_struct()
+        keep.append(k)
+    return arr, keep
+
+
+class BatchPlan:
+    """Owning wrapper of a pcms_batch_plan; holds the problems' tensors."""
+
+    def __init__(self, problems, o: Optional[BatchOpts] = None):
+        self.problems = list(problems)
+        arr, self._keep = _problem_array(self.problems)
+        self._opts = batch_opts() if o is None else o
+        h = ctypes.c_void_p()
+        _check(lib().pcms_batch_plan_create(arr, len(self.problems), ctypes.byref(self._opts),
+                                            ctypes.byref(h)))
+        self.handle = h
+
+    def exec(self, stream=None, summary: Optional[torch.Tensor] = None,
+             allow_status_errors=True) -> int:
+        allow = _STATUS_CODES if allow_status_errors else ()
+        return _check(lib().pcms_batch_plan_exec(self.handle, _stream(stream), _ptr(summary)),
+                      allow)
+
+    def free(self):
+        if getattr(self, "handle", None):
+            lib().pcms_batch_plan_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def pcms_autotune(problems, o: Optional[BatchOpts] = None, cache_path: Optional[str] = None,
+                  stream=None) -> TuneResult:
+    arr, keep = _problem_array(list(problems))
+    o = batch_opts() if o is None else o
+    res = TuneResult()
+    _check(lib().pcms_autotune(arr, len(problems), ctypes.byref(o),
+                               None if cache_path is None else cache_path.encode(),
+                               _stream(stream), ctypes.byref(res)))
+    return res
+
+
+def batch_problem_of(prob, dev, out=None) -> BatchProblem:
+    """BatchProblem of a synth.Problem, with its arrays copied to `dev`."""
+    src = torch.from_numpy(prob.src).to(dev)
+    vals = torch.from_numpy(prob.vals).to(dev)
+    tgt = torch.from_numpy(prob.tgt).to(dev)
+    return BatchProblem(src, vals, tgt, prob.degree, radius_of(prob), prob.k_cap,
+                        inv_scale=prob.inv_scale, out=out)

@@ -112,3 +112,51 @@ def test_grid_and_neighbor_argument_checks():
     assert L.pcms_mls_transfer_grid(None, FAKE, 1, FAKE, 5, 1, ctypes.byref(r), 8, None, None,
                                     FAKE, None) == pcms.PCMS_ERR_ARG
     assert L.pcms_grid_free(None) == pcms.PCMS_OK
+
+
+def _problem(**kw):
+    a = dict(src=0x1000, n_src=100, dim=2, basis_degree=1, src_vals=0x1000, n_fields=1, k_cap=32,
+             tgt=0x1000, n_tgt=10, radius=pcms.radius(pcms.RADIUS_FIXED, r=0.1), inv_scale=None,
+             tgt_vals=0x1000, status=None)
+    a.update(kw)
+    return pcms.Problem(**a)
+
+
+def _plan(probs, o=None):
+    arr = (pcms.Problem * max(len(probs), 1))(*probs)
+    h = ctypes.c_void_p()
+    return pcms.lib().pcms_batch_plan_create(arr if probs else None, len(probs),
+                                             None if o is None else ctypes.byref(o),
+                                             ctypes.byref(h))
+
+
+@needs_lib
+def test_batch_defaults():
+    o = pcms.BatchOpts()
+    pcms.lib().pcms_batch_opts_default(ctypes.byref(o))
+    assert o.weight == 0 and o.precision == pcms.MIXED_REFINE and o.block == 0
+    assert o.cell_factor == 0.0 and o.tune_cache is None
+
+
+@needs_lib
+@pytest.mark.parametrize("kw,msg", [
+    (dict(dim=6), "problem 1: dim"), (dict(n_src=0), "problem 1: n_src"),
+    (dict(k_cap=2), "problem 1: k_cap"), (dict(src=None), "problem 1: src"),
+    (dict(tgt_vals=None), "problem 1: src_vals, tgt and tgt_vals"),
+    (dict(radius=pcms.radius(pcms.RADIUS_KNN, k=500)), "problem 1: KNN k"),
+])
+def test_batch_plan_rejects_bad_problems(kw, msg):
+    assert _plan([_problem(), _problem(**kw)]) == pcms.PCMS_ERR_ARG
+    assert msg in pcms.last_error()
+
+
+@needs_lib
+def test_batch_plan_rejects_bad_options():
+    assert _plan([]) == pcms.PCMS_ERR_ARG
+    assert _plan([_problem()], pcms.batch_opts(block=96)) == pcms.PCMS_ERR_ARG
+    assert _plan([_problem()], pcms.batch_opts(cell_factor=5.0)) == pcms.PCMS_ERR_ARG
+    assert _plan([_problem()], pcms.batch_opts(precision=4)) == pcms.PCMS_ERR_ARG
+    assert _plan([_problem()], pcms.batch_opts(lam=-1.0)) == pcms.PCMS_ERR_ARG
+    L = pcms.lib()
+    assert L.pcms_batch_plan_exec(None, None, None) == pcms.PCMS_ERR_ARG
+    assert L.pcms_batch_plan_free(None) == pcms.PCMS_OK
