@@ -14,9 +14,10 @@
 // factorisation across all fields.
 //
 // Precision: FP64 assembles G in FP64.  MIXED forms xi_e and w_e in FP32 and
-// accumulates G in FP32; the factorisation and everything after it are FP64.
-// MIXED_REFINE adds FP64 iterative refinement y += G^{-1}(e_0 - G y) with the
-// residual formed in FP64 from the same per-neighbour data (one step unless
+// accumulates G in FP32; the factorisation, the solve and the evaluation
+// pass are FP64 (FP64 per-neighbour data).  MIXED_REFINE adds FP64 iterative
+// refinement y += G32^{-1}(e_0 - G y) with the residual formed from FP64
+// per-neighbour data, which converges to the FP64 result (one step unless
 // the target is ill-conditioned).  In the mixed modes with lambda = 0 field
 // values are centred on the first kept neighbour's value.
 #pragma once
@@ -360,11 +361,12 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
         for (int u = 0; u < M; ++u) y[u] = u == 0 ? 1.0 : 0.0;
         chol_solve<M>(R, idg, y);
         if (ok && MIXED && a.refine) {
-            // Iterative refinement: y += G32^{-1} (e_0 - (G + lambda I) y), the
-            // residual formed in FP64 from the same FP32 per-neighbour data.
-            // One step normally suffices; ill-conditioned targets take up to
-            // kMaxRefine, and a correction that does not shrink marks the
-            // target singular at FP32 assembly accuracy.
+            // Iterative refinement: y += G32^{-1} (e_0 - (G + lambda I) y) with
+            // the residual formed entirely in FP64 (FP64 weights and monomials),
+            // so y converges to the FP64 solution and the FP32 factor serves
+            // only as the preconditioner.  One step normally suffices;
+            // ill-conditioned targets take up to kMaxRefine, and a correction
+            // that does not shrink marks the target singular at FP32 accuracy.
             for (int step = 0; step < kMaxRefine; ++step) {
                 double res[M];
 #pragma unroll
@@ -376,15 +378,15 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                     load_neighbours<D, G, kRef>(S, a.spts, e0, n, sb, okn, pe);
 #pragma unroll
                     for (int j = 0; j < kRef; ++j) {
-                        TA p[M], w;
-                        neighbour_data<D, P, UNIT, TA>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p,
-                                                       w);
+                        double p[M], w;
+                        neighbour_data<D, P, UNIT, double>(gp, S.t, sb[j], inv_h, inv_r2, a.weight,
+                                                           p, w);
                         double py = 0.0;
 #pragma unroll
-                        for (int u = 0; u < M; ++u) py = __builtin_fma((double)p[u], y[u], py);
-                        const double c = okn[j] ? -(double)w * py : 0.0;
+                        for (int u = 0; u < M; ++u) py = __builtin_fma(p[u], y[u], py);
+                        const double c = okn[j] ? -w * py : 0.0;
 #pragma unroll
-                        for (int u = 0; u < M; ++u) res[u] = __builtin_fma(c, (double)p[u], res[u]);
+                        for (int u = 0; u < M; ++u) res[u] = __builtin_fma(c, p[u], res[u]);
                     }
                 }
 #pragma unroll
@@ -437,12 +439,12 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                 }
 #pragma unroll
                 for (int j = 0; j < kApply; ++j) {
-                    TA p[M], w;
-                    neighbour_data<D, P, UNIT, TA>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p, w);
+                    double p[M], w;
+                    neighbour_data<D, P, UNIT, double>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p, w);
                     double py = 0.0;
 #pragma unroll
-                    for (int u = 0; u < M; ++u) py = __builtin_fma((double)p[u], y[u], py);
-                    const double N = ok[j] ? (double)w * py : 0.0;
+                    for (int u = 0; u < M; ++u) py = __builtin_fma(p[u], y[u], py);
+                    const double N = ok[j] ? w * py : 0.0;
 #pragma unroll
                     for (int l = 0; l < kFieldChunk; ++l)
                         acc[l] = __builtin_fma(N, fv[j][l] - fref[l], acc[l]);
