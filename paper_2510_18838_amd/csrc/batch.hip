@@ -18,9 +18,7 @@
 #include <algorithm>
 #include <climits>
 
-#include "fit.h"
-#include "internal.h"
-#include "launch_common.h"
+#include "batch_kernel.h"
 
 namespace pcms {
 
@@ -267,95 +265,6 @@ __global__ void k_batch_tperm(const int64_t *__restrict__ pref, int n,
     }
 }
 
-struct BArgs {
-    const BatchProb *probs;
-    const GridParams *params;
-    const int *cs;
-    const double *spts;
-    const int *perm;
-    const int *tperm;
-    const double *svals;
-    const int4 *items;
-    int n_items;
-    int *counter;
-    int32_t *summary;
-    int weight;
-    int refine;
-    double lambda;
-};
-
-// Persistent transfer: each block takes work items (problem, first sorted
-// target, count) from the counter until the queue is empty; its threads run
-// one target each with the problem's (dimension, degree, metric) variant of
-// the one-problem code.  Problems of dimension 1-3 only.
-template <bool MIXED>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-k_batch_transfer(BArgs b)
-{
-    extern __shared__ int lds[];
-    __shared__ int s_item;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(b.counter, 1);
-        __syncthreads();
-        const int it = s_item;
-        __syncthreads();   // every thread has read s_item before it is rewritten
-        if (it >= b.n_items) break;
-        const int4 w = b.items[it];
-        const int q = w.x;
-        const BatchProb &P = b.probs[q];
-        KArgs a{};
-        a.gp = b.params + q;
-        a.cs = b.cs + P.cs_off;
-        a.spts = b.spts + P.spts_off;
-        a.perm = b.perm + P.src_off;
-        a.tgt = P.tgt;
-        a.tperm = b.tperm + P.tgt_off;
-        a.n_tgt = P.n_tgt;
-        a.mode = P.mode;
-        a.k = P.k;
-        a.n_min = P.n_min;
-        a.max_iter = P.max_iter;
-        a.r = P.r;
-        a.k_cap = P.k_cap;
-        a.words = P.words;
-        a.stride = P.stride;
-        a.svals = b.svals + P.sval_off;
-        a.nf = P.nf;
-        a.nfs = P.nfs;
-        a.weight = b.weight;
-        a.refine = b.refine;
-        a.lambda = b.lambda;
-        a.out = P.out;
-        a.status = P.status;
-        a.summary = b.summary;
-        const int slot = (int)threadIdx.x;
-        const bool active = slot < w.z;
-        int st = 0;
-        if (active) {
-            const GridParams gp = b.params[q];
-            const int i = w.y + slot;
-            int *L = lds + slot * P.stride;
-            const Grp<1> g{0};
-            const int cls = (P.dim * 3 + P.degree) * 2 + P.unit;
-#define PCMS_BCASE(DD, PP, UU)                                                   \
-    case (DD * 3 + PP) * 2 + UU:                                                 \
-        st = xfer_target<DD, PP, MIXED, (bool)UU, 1>(a, gp, i, L, g);            \
-        break;
-            switch (cls) {
-                PCMS_BCASE(1, 0, 1) PCMS_BCASE(1, 1, 1) PCMS_BCASE(1, 2, 1)
-                PCMS_BCASE(2, 0, 1) PCMS_BCASE(2, 1, 1) PCMS_BCASE(2, 2, 1)
-                PCMS_BCASE(3, 0, 1) PCMS_BCASE(3, 1, 1) PCMS_BCASE(3, 2, 1)
-                PCMS_BCASE(1, 0, 0) PCMS_BCASE(1, 1, 0) PCMS_BCASE(1, 2, 0)
-                PCMS_BCASE(2, 0, 0) PCMS_BCASE(2, 1, 0) PCMS_BCASE(2, 2, 0)
-                PCMS_BCASE(3, 0, 0) PCMS_BCASE(3, 1, 0) PCMS_BCASE(3, 2, 0)
-            default: break;
-            }
-#undef PCMS_BCASE
-        }
-        add_summary(b.summary, st, active);
-    }
-}
-
 __global__ void k_copy_summary(const int32_t *from, int32_t *to)
 {
     if (threadIdx.x < 4) to[threadIdx.x] = from[threadIdx.x];
@@ -506,10 +415,9 @@ pcms_status batch_setup(BatchPlan &p)
     int per_cu = 0, dev = 0, cus = 0;
     PCMS_HIP(hipGetDevice(&dev));
     PCMS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    if (p.precision == PCMS_FP64)
-        PCMS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_transfer<false>, p.block, shm));
-    else
-        PCMS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_transfer<true>, p.block, shm));
+    per_cu = p.precision == PCMS_FP64    ? batch_occupancy<PCMS_FP64>(p.block, shm)
+           : p.precision == PCMS_MIXED   ? batch_occupancy<PCMS_MIXED>(p.block, shm)
+                                         : batch_occupancy<PCMS_MIXED_REFINE>(p.block, shm);
     p.persist_blocks = std::max(1, std::min(p.n_items, std::max(per_cu, 1) * std::max(cus, 1)));
     // host views of every problem's grid (for the problems of dimension > 3)
     p.views.assign(n, Grid{});
@@ -579,14 +487,14 @@ pcms_status batch_enqueue(BatchPlan &p, hipStream_t s)
         b.counter = p.counter;
         b.summary = p.summary;
         b.weight = p.weight;
-        b.refine = p.precision == PCMS_MIXED_REFINE;
         b.lambda = p.lambda;
         const size_t shm = (size_t)p.block * p.max_stride * sizeof(int);
-        if (p.precision == PCMS_FP64)
-            hipLaunchKernelGGL(k_batch_transfer<false>, dim3(p.persist_blocks), dim3(p.block), shm, s, b);
-        else
-            hipLaunchKernelGGL(k_batch_transfer<true>, dim3(p.persist_blocks), dim3(p.block), shm, s, b);
-        PCMS_HIP(hipGetLastError());
+        st = p.precision == PCMS_FP64
+               ? batch_launch<PCMS_FP64>(b, p.persist_blocks, p.block, shm, s)
+             : p.precision == PCMS_MIXED
+               ? batch_launch<PCMS_MIXED>(b, p.persist_blocks, p.block, shm, s)
+               : batch_launch<PCMS_MIXED_REFINE>(b, p.persist_blocks, p.block, shm, s);
+        if (st != PCMS_OK) return st;
     }
     for (int q : p.outer) {
         const BatchProb &B = p.hp[q];

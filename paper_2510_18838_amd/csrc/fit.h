@@ -88,30 +88,30 @@ PCMS_HD PCMS_INLINE constexpr int tri(int a, int b)
     return a * M - a * (a - 1) / 2 + (b - a);
 }
 
-// In-place Cholesky of the packed SPD matrix A (upper triangle rows),
+// In-place Cholesky of the packed SPD matrix A (upper triangle rows), in T,
 // overwriting it with the factor R = L^T (A = R^T R).  Returns false when a
 // pivot is not above 1e-13 * max diag(A).
-template <int M>
-PCMS_HD PCMS_INLINE bool cholesky(double (&A)[M * (M + 1) / 2], double (&inv_diag)[M])
+template <int M, typename T>
+PCMS_HD PCMS_INLINE bool cholesky(T (&A)[M * (M + 1) / 2], T (&inv_diag)[M])
 {
-    double maxd = 0.0;
+    T maxd = T(0);
 #pragma unroll
     for (int i = 0; i < M; ++i) maxd = fmax(maxd, A[tri<M>(i, i)]);
-    const double tau = 1e-13 * maxd;
-    bool ok = maxd > 0.0;
+    const T tau = T(1e-13) * maxd;
+    bool ok = maxd > T(0);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        double s = A[tri<M>(j, j)];
+        T s = A[tri<M>(j, j)];
 #pragma unroll
         for (int k = 0; k < j; ++k) s = __builtin_fma(-A[tri<M>(k, j)], A[tri<M>(k, j)], s);
         ok = ok && (s > tau);
-        double d = sqrt(fmax(s, 1e-300));
-        double id = 1.0 / d;
+        T d = sqrt(fmax(s, sizeof(T) == sizeof(double) ? T(1e-300) : T(1e-30)));
+        T id = T(1) / d;
         A[tri<M>(j, j)] = d;
         inv_diag[j] = id;
 #pragma unroll
         for (int i = j + 1; i < M; ++i) {
-            double x = A[tri<M>(j, i)];
+            T x = A[tri<M>(j, i)];
 #pragma unroll
             for (int k = 0; k < j; ++k) x = __builtin_fma(-A[tri<M>(k, j)], A[tri<M>(k, i)], x);
             A[tri<M>(j, i)] = x * id;
@@ -120,24 +120,25 @@ PCMS_HD PCMS_INLINE bool cholesky(double (&A)[M * (M + 1) / 2], double (&inv_dia
     return ok;
 }
 
-// Solves R^T R x = b in place with the packed factor R.
-template <int M>
-PCMS_HD PCMS_INLINE void chol_solve(const double (&R)[M * (M + 1) / 2],
-                                    const double (&inv_diag)[M], double (&x)[M])
+// Solves R^T R x = b in place with the packed factor R (entries of type T),
+// in FP64 arithmetic.
+template <int M, typename T>
+PCMS_HD PCMS_INLINE void chol_solve(const T (&R)[M * (M + 1) / 2], const T (&inv_diag)[M],
+                                    double (&x)[M])
 {
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         double s = x[i];
 #pragma unroll
-        for (int k = 0; k < i; ++k) s = __builtin_fma(-R[tri<M>(k, i)], x[k], s);
-        x[i] = s * inv_diag[i];
+        for (int k = 0; k < i; ++k) s = __builtin_fma(-(double)R[tri<M>(k, i)], x[k], s);
+        x[i] = s * (double)inv_diag[i];
     }
 #pragma unroll
     for (int i = M - 1; i >= 0; --i) {
         double s = x[i];
 #pragma unroll
-        for (int k = i + 1; k < M; ++k) s = __builtin_fma(-R[tri<M>(i, k)], x[k], s);
-        x[i] = s * inv_diag[i];
+        for (int k = i + 1; k < M; ++k) s = __builtin_fma(-(double)R[tri<M>(i, k)], x[k], s);
+        x[i] = s * (double)inv_diag[i];
     }
 }
 
@@ -163,7 +164,6 @@ struct KArgs {
     int nf;
     int nfs;               // padded_dim(nf): 16-byte aligned value records
     int weight;
-    int refine;
     double lambda;
     double *out;           // [nf][n_tgt]
     // outputs
@@ -300,15 +300,17 @@ PCMS_HD PCMS_INLINE void neighbour_data(const GridParams &gp, const double (&t)[
 }
 
 // Field transfer of the target at sorted slot i; returns its status.
-template <int D, int P, bool MIXED, bool UNIT, int G>
+template <int D, int P, int PREC, bool UNIT, int G>
 PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i, int *L, Grp<G> g)
 {
+    constexpr bool MIXED = PREC != PCMS_FP64;
+    constexpr bool REFINE = PREC == PCMS_MIXED_REFINE;
     constexpr int M = Basis<D, P>::M;
     constexpr int MM = Basis<D, P>::MM;
     using TA = typename std::conditional<MIXED, float, double>::type;   // assembly type
     // neighbours per lane whose loads are issued together, per pass (fewer
     // where the pass holds more live registers)
-    constexpr int kAsm = MIXED ? 4 : 2, kRef = 2, kApply = 2;
+    constexpr int kAsm = MIXED ? 4 : 2, kRef = 1, kApply = 2;
     const int ti = a.tperm[i];
     Search<D, UNIT, G> S{gp, a.cs, a.spts, a.perm, {}, L, a.k_cap, a.words, g};
     load_point<D>(a.tgt, ti, S.t);
@@ -346,28 +348,38 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
         }
 #pragma unroll
         for (int j = 0; j < MM; ++j) Gm[j] = g.sum(Gm[j]);
-        // FP64 factor of G + lambda I; recomputed (bit-identically) after each
-        // refinement pass rather than kept live across it
-        double R[MM], idg[M];
-        auto factor = [&]() {
+        bool ok;
+#pragma unroll
+        for (int u = 0; u < M; ++u) y[u] = u == 0 ? 1.0 : 0.0;
+        if (!REFINE) {
+            // FP64 factor of G + lambda I and the solve y = G^{-1} e_0
+            double R[MM], idg[M];
 #pragma unroll
             for (int j = 0; j < MM; ++j) R[j] = (double)Gm[j];
 #pragma unroll
             for (int u = 0; u < M; ++u) R[tri<M>(u, u)] += a.lambda;
-            return cholesky<M>(R, idg);
-        };
-        bool ok = factor();
+            ok = cholesky<M, double>(R, idg);
+            chol_solve<M, double>(R, idg, y);
+        } else {
+            // Iterative refinement with an FP32 factor of the FP32 moments as
+            // the preconditioner: y += G32^{-1} (e_0 - (G + lambda I) y), the
+            // residual formed entirely in FP64 (FP64 weights and monomials),
+            // so y converges to the FP64 solution.  One or two steps normally
+            // suffice; ill-conditioned targets take up to kMaxRefine, and a
+            // correction that does not shrink marks the target singular at
+            // FP32 accuracy.
+            TA idg[M];
 #pragma unroll
-        for (int u = 0; u < M; ++u) y[u] = u == 0 ? 1.0 : 0.0;
-        chol_solve<M>(R, idg, y);
-        if (ok && MIXED && a.refine) {
-            // Iterative refinement: y += G32^{-1} (e_0 - (G + lambda I) y) with
-            // the residual formed entirely in FP64 (FP64 weights and monomials),
-            // so y converges to the FP64 solution and the FP32 factor serves
-            // only as the preconditioner.  One step normally suffices;
-            // ill-conditioned targets take up to kMaxRefine, and a correction
-            // that does not shrink marks the target singular at FP32 accuracy.
-            for (int step = 0; step < kMaxRefine; ++step) {
+            for (int u = 0; u < M; ++u) Gm[tri<M>(u, u)] += (TA)a.lambda;
+            ok = cholesky<M, TA>(Gm, idg);
+            chol_solve<M, TA>(Gm, idg, y);
+            for (int step = 0; ok && step < kMaxRefine; ++step) {
+#ifndef PCMS_HOST_EMULATION
+                // keeps the compiler from hoisting the FP64 conversions of the
+                // factor out of the loop (55 live doubles instead of floats)
+#pragma unroll
+                for (int j = 0; j < MM; ++j) __asm__ volatile("" : "+v"(Gm[j]));
+#endif
                 double res[M];
 #pragma unroll
                 for (int u = 0; u < M; ++u) res[u] = 0.0;
@@ -392,8 +404,7 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
 #pragma unroll
                 for (int u = 0; u < M; ++u)
                     res[u] = g.sum(res[u]) + ((u == 0 ? 1.0 : 0.0) - a.lambda * y[u]);
-                factor();
-                chol_solve<M>(R, idg, res);
+                chol_solve<M, TA>(Gm, idg, res);
                 double ny = 0.0, nd = 0.0;
 #pragma unroll
                 for (int u = 0; u < M; ++u) {

@@ -1,0 +1,107 @@
+// The one-problem neighbour-list and field-transfer kernels (one lane per
+// target, targets in tiled Morton order so that the lanes of a wave search
+// overlapping stencils), instantiated per dimension in mls_d1.hip ..
+// mls_d5.hip so that the variants compile in parallel.  The per-target work
+// (search, moment assembly, Cholesky, evaluation) is in fit.h / search.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fit.h"
+#include "launch_common.h"
+
+namespace pcms {
+
+// Lanes per target (G consecutive lanes of a wave); the block's targets are
+// consecutive in processing order and each owns `stride` LDS words.
+#ifndef PCMS_LANES_PER_TARGET
+#define PCMS_LANES_PER_TARGET 1
+#endif
+constexpr int kGroup = PCMS_LANES_PER_TARGET;
+
+using KernelFn = void (*)(KArgs);
+
+// Kernel of dimension D for (degree, precision, unit metric); defined in
+// mls_d<D>.hip.
+template <int D>
+KernelFn transfer_kernel(int degree, int precision, bool unit);
+template <int D>
+KernelFn nbr_kernel(bool unit);
+
+namespace {
+
+template <int D, bool UNIT, int G>
+__global__ void __launch_bounds__(256) k_neighbors(KArgs a)
+{
+    extern __shared__ int lds[];
+    const int lb = logical_block(a.n_blocks);
+    if (lb >= a.n_blocks) return;
+    const int slot = (int)threadIdx.x / G;
+    const int i = lb * ((int)blockDim.x / G) + slot;
+    const bool active = i < a.n_tgt;   // uniform within a group
+    const Grp<G> g{(int)(threadIdx.x & (G - 1))};
+    int st = 0;
+    if (active) {
+        const GridParams gp = *a.gp;
+        st = nbr_target<D, UNIT, G>(a, gp, i, lds + slot * a.stride, g);
+    }
+    add_summary(a.summary, st, active && g.q == 0);
+}
+
+// Waves per SIMD the register allocator targets (168 VGPRs for 3).
+#ifndef PCMS_WAVES_REFINE
+#define PCMS_WAVES_REFINE 3
+#endif
+template <int PREC>
+constexpr int waves_for() { return PREC == PCMS_MIXED_REFINE ? PCMS_WAVES_REFINE : 3; }
+
+template <int D, int P, int PREC, bool UNIT, int G>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for<PREC>())))
+k_transfer(KArgs a)
+{
+    extern __shared__ int lds[];
+    const int lb = logical_block(a.n_blocks);
+    if (lb >= a.n_blocks) return;
+    const int slot = (int)threadIdx.x / G;
+    const int i = lb * ((int)blockDim.x / G) + slot;
+    const bool active = i < a.n_tgt;   // uniform within a group
+    const Grp<G> g{(int)(threadIdx.x & (G - 1))};
+    int st = 0;
+    if (active) {
+        const GridParams gp = *a.gp;
+        st = xfer_target<D, P, PREC, UNIT, G>(a, gp, i, lds + slot * a.stride, g);
+    }
+    add_summary(a.summary, st, active && g.q == 0);
+}
+
+template <int D, int P, bool UNIT>
+KernelFn pick_prec(int precision)
+{
+    return precision == PCMS_FP64  ? (KernelFn)k_transfer<D, P, PCMS_FP64, UNIT, kGroup>
+         : precision == PCMS_MIXED ? (KernelFn)k_transfer<D, P, PCMS_MIXED, UNIT, kGroup>
+                                   : (KernelFn)k_transfer<D, P, PCMS_MIXED_REFINE, UNIT, kGroup>;
+}
+
+}  // namespace
+
+// Body of the per-dimension definitions.
+#define PCMS_DEFINE_DIM_KERNELS(DD)                                                    \
+    template <>                                                                        \
+    KernelFn transfer_kernel<DD>(int degree, int precision, bool unit)                 \
+    {                                                                                  \
+        if (unit)                                                                      \
+            return degree == 0 ? pick_prec<DD, 0, true>(precision)                     \
+                 : degree == 1 ? pick_prec<DD, 1, true>(precision)                     \
+                               : pick_prec<DD, 2, true>(precision);                    \
+        return degree == 0 ? pick_prec<DD, 0, false>(precision)                        \
+             : degree == 1 ? pick_prec<DD, 1, false>(precision)                        \
+                           : pick_prec<DD, 2, false>(precision);                       \
+    }                                                                                  \
+    template <>                                                                        \
+    KernelFn nbr_kernel<DD>(bool unit)                                                 \
+    {                                                                                  \
+        return unit ? (KernelFn)k_neighbors<DD, true, kGroup>                          \
+                    : (KernelFn)k_neighbors<DD, false, kGroup>;                        \
+    }
+
+}  // namespace pcms

@@ -1,63 +1,14 @@
-// Neighbour-list and field-transfer kernels: one lane per target, targets in
-// tiled Morton order so that the lanes of a wave search overlapping stencils.  The
-// per-target work (search, moment assembly, Cholesky, evaluation) is in
-// fit.h / search.h; this file holds the kernels and their launchers.
+// Launchers of the one-problem neighbour-list and field-transfer kernels
+// (kernels.h): LDS sizing, block choice, XCD-aware grid, variant dispatch.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
-#include "fit.h"
 #include "internal.h"
-#include "launch_common.h"
+#include "kernels.h"
 
 namespace pcms {
 
 namespace {
-
-// Lanes per target (G consecutive lanes of a wave); the block's targets are
-// consecutive in processing order and each owns `stride` LDS words.
-#ifndef PCMS_LANES_PER_TARGET
-#define PCMS_LANES_PER_TARGET 1
-#endif
-constexpr int kGroup = PCMS_LANES_PER_TARGET;
-
-template <int D, bool UNIT, int G>
-__global__ void __launch_bounds__(256) k_neighbors(KArgs a)
-{
-    extern __shared__ int lds[];
-    const int lb = logical_block(a.n_blocks);
-    if (lb >= a.n_blocks) return;
-    const int slot = (int)threadIdx.x / G;
-    const int i = lb * ((int)blockDim.x / G) + slot;
-    const bool active = i < a.n_tgt;   // uniform within a group
-    const Grp<G> g{(int)(threadIdx.x & (G - 1))};
-    int st = 0;
-    if (active) {
-        const GridParams gp = *a.gp;
-        st = nbr_target<D, UNIT, G>(a, gp, i, lds + slot * a.stride, g);
-    }
-    add_summary(a.summary, st, active && g.q == 0);
-}
-
-// Three waves per SIMD: the register allocator fits 168 VGPRs (the fit's
-// moment and factor arrays spill a little around the refinement pass), which
-// measured faster than two waves without spills.
-template <int D, int P, bool MIXED, bool UNIT, int G>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_transfer(KArgs a)
-{
-    extern __shared__ int lds[];
-    const int lb = logical_block(a.n_blocks);
-    if (lb >= a.n_blocks) return;
-    const int slot = (int)threadIdx.x / G;
-    const int i = lb * ((int)blockDim.x / G) + slot;
-    const bool active = i < a.n_tgt;   // uniform within a group
-    const Grp<G> g{(int)(threadIdx.x & (G - 1))};
-    int st = 0;
-    if (active) {
-        const GridParams gp = *a.gp;
-        st = xfer_target<D, P, MIXED, UNIT, G>(a, gp, i, lds + slot * a.stride, g);
-    }
-    add_summary(a.summary, st, active && g.q == 0);
-}
 
 __global__ void k_zero_ints(int32_t *p, int n)
 {
@@ -65,49 +16,26 @@ __global__ void k_zero_ints(int32_t *p, int n)
     if (i < n) p[i] = 0;
 }
 
-using KernelFn = void (*)(KArgs);
-
-template <int D, bool UNIT>
-KernelFn pick_nbr()
+KernelFn xfer_for(int d, int p, int precision, bool unit)
 {
-    return k_neighbors<D, UNIT, kGroup>;
-}
-
-template <int D, int P, bool UNIT>
-KernelFn pick_xfer(bool mixed)
-{
-    return mixed ? (KernelFn)k_transfer<D, P, true, UNIT, kGroup>
-                 : (KernelFn)k_transfer<D, P, false, UNIT, kGroup>;
-}
-
-template <bool UNIT>
-KernelFn xfer_table(int d, int p, bool mixed)
-{
-#define PCMS_CASE(DD)                                               \
-    case DD:                                                        \
-        return p == 0 ? pick_xfer<DD, 0, UNIT>(mixed)               \
-             : p == 1 ? pick_xfer<DD, 1, UNIT>(mixed)               \
-                      : pick_xfer<DD, 2, UNIT>(mixed);
     switch (d) {
-        PCMS_CASE(1)
-        PCMS_CASE(2)
-        PCMS_CASE(3)
-        PCMS_CASE(4)
-        PCMS_CASE(5)
+    case 1: return transfer_kernel<1>(p, precision, unit);
+    case 2: return transfer_kernel<2>(p, precision, unit);
+    case 3: return transfer_kernel<3>(p, precision, unit);
+    case 4: return transfer_kernel<4>(p, precision, unit);
+    case 5: return transfer_kernel<5>(p, precision, unit);
     }
-#undef PCMS_CASE
     return nullptr;
 }
 
-template <bool UNIT>
-KernelFn nbr_table(int d)
+KernelFn nbr_for(int d, bool unit)
 {
     switch (d) {
-    case 1: return pick_nbr<1, UNIT>();
-    case 2: return pick_nbr<2, UNIT>();
-    case 3: return pick_nbr<3, UNIT>();
-    case 4: return pick_nbr<4, UNIT>();
-    case 5: return pick_nbr<5, UNIT>();
+    case 1: return nbr_kernel<1>(unit);
+    case 2: return nbr_kernel<2>(unit);
+    case 3: return nbr_kernel<3>(unit);
+    case 4: return nbr_kernel<4>(unit);
+    case 5: return nbr_kernel<5>(unit);
     }
     return nullptr;
 }
@@ -177,7 +105,7 @@ pcms_status launch_neighbors(const LaunchSpec &ls, int32_t *nbr, int32_t *n_kept
     a.n_found = n_found;
     a.r2 = r2;
     a.status = status;
-    KernelFn fn = unit_metric(ls.grid) ? nbr_table<true>(ls.grid->dim) : nbr_table<false>(ls.grid->dim);
+    KernelFn fn = nbr_for(ls.grid->dim, unit_metric(ls.grid));
     const int launch = ((a.n_blocks + 7) / 8) * 8;
     const size_t shm = (size_t)(block / kGroup) * target_stride(ls) * sizeof(int);
     hipLaunchKernelGGL(fn, dim3(launch), dim3(block), shm, s, a);
@@ -196,13 +124,10 @@ pcms_status launch_transfer(const LaunchSpec &ls, const double *svals, int n_fie
     a.nf = n_fields;
     a.nfs = padded_dim(n_fields);
     a.weight = weight;
-    a.refine = precision == PCMS_MIXED_REFINE;
     a.lambda = lambda;
     a.out = out;
     a.status = status;
-    const bool mixed = precision != PCMS_FP64;
-    KernelFn fn = unit_metric(ls.grid) ? xfer_table<true>(ls.grid->dim, degree, mixed)
-                                       : xfer_table<false>(ls.grid->dim, degree, mixed);
+    KernelFn fn = xfer_for(ls.grid->dim, degree, precision, unit_metric(ls.grid));
     const int launch = ((a.n_blocks + 7) / 8) * 8;
     const size_t shm = (size_t)(block / kGroup) * target_stride(ls) * sizeof(int);
     hipLaunchKernelGGL(fn, dim3(launch), dim3(block), shm, s, a);

@@ -267,30 +267,32 @@ void run_nbr(const KArgs &a, const GridParams &gp)
     run_groups<G>(a, [&](int i, int *L, Grp<G> g) { nbr_target<D, UNIT, G>(a, gp, i, L, g); });
 }
 
-template <int D, int P, bool MIXED, bool UNIT, int G>
+template <int D, int P, int PREC, bool UNIT, int G>
 void run_xfer(const KArgs &a, const GridParams &gp)
 {
-    run_groups<G>(a, [&](int i, int *L, Grp<G> g) { xfer_target<D, P, MIXED, UNIT, G>(a, gp, i, L, g); });
+    run_groups<G>(a, [&](int i, int *L, Grp<G> g) { xfer_target<D, P, PREC, UNIT, G>(a, gp, i, L, g); });
 }
 
 template <int D, bool UNIT, int G>
-void dispatch_g(int op, const KArgs &a, const GridParams &gp, int degree, bool mixed)
+void dispatch_g(int op, const KArgs &a, const GridParams &gp, int degree, int precision)
 {
     if (op == 0) return run_nbr<D, UNIT, G>(a, gp);
 #define X(PP)                                                                  \
     if (degree == PP) {                                                        \
-        if (mixed) return run_xfer<D, PP, true, UNIT, G>(a, gp);               \
-        return run_xfer<D, PP, false, UNIT, G>(a, gp);                         \
+        if (precision == PCMS_MIXED) return run_xfer<D, PP, PCMS_MIXED, UNIT, G>(a, gp); \
+        if (precision == PCMS_MIXED_REFINE)                                    \
+            return run_xfer<D, PP, PCMS_MIXED_REFINE, UNIT, G>(a, gp);          \
+        return run_xfer<D, PP, PCMS_FP64, UNIT, G>(a, gp);                     \
     }
     X(0) X(1) X(2)
 #undef X
 }
 
 template <int D, bool UNIT>
-void dispatch(int op, const KArgs &a, const GridParams &gp, int group, int degree, bool mixed)
+void dispatch(int op, const KArgs &a, const GridParams &gp, int group, int degree, int precision)
 {
-    if (group == 4) return dispatch_g<D, UNIT, 4>(op, a, gp, degree, mixed);
-    return dispatch_g<D, UNIT, 1>(op, a, gp, degree, mixed);
+    if (group == 4) return dispatch_g<D, UNIT, 4>(op, a, gp, degree, precision);
+    return dispatch_g<D, UNIT, 1>(op, a, gp, degree, precision);
 }
 
 }  // namespace
@@ -396,7 +398,6 @@ int main(int argc, char **argv)
     a.nf = (int)nf;
     a.nfs = nfs;
     a.weight = weight;
-    a.refine = precision == PCMS_MIXED_REFINE;
     a.lambda = lambda;
     std::vector<double> out((size_t)(nf * n_tgt), 0.0);
     std::vector<int32_t> nbr((size_t)(n_tgt * k_cap), -1), n_kept(n_tgt), n_found(n_tgt);
@@ -410,11 +411,10 @@ int main(int argc, char **argv)
     a.status = status.data();
     bool unit = true;
     for (int q = 0; q < dim; ++q) unit = unit && g[q] == 1.0;
-    const bool mixed = precision != PCMS_FP64;
 #define DIMCASE(DD)                                                                 \
     case DD:                                                                        \
-        if (unit) dispatch<DD, true>(op, a, gp, group, degree, mixed);              \
-        else dispatch<DD, false>(op, a, gp, group, degree, mixed);                  \
+        if (unit) dispatch<DD, true>(op, a, gp, group, degree, precision);              \
+        else dispatch<DD, false>(op, a, gp, group, degree, precision);                  \
         break;
     switch (dim) {
         DIMCASE(1) DIMCASE(2) DIMCASE(3) DIMCASE(4) DIMCASE(5)
