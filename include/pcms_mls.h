@@ -99,10 +99,13 @@ typedef struct {
  *   FP64:         everything in FP64.
  *   MIXED:        weights and the moment matrix G = P^T W P in FP32 with FP32
  *                 accumulation; Cholesky, solve and evaluation in FP64.
- *   MIXED_REFINE: MIXED plus FP64 iterative refinement of the shape
- *                 functional G^{-1} e_0 (residual formed in FP64 from the
- *                 same per-neighbour data): one step, up to four for
- *                 ill-conditioned targets. */
+ *   MIXED_REFINE: FP32 moment matrix and an FP32 Cholesky factor of it as
+ *                 the preconditioner of FP64 iterative refinement of the
+ *                 shape functional y = G^{-1} e_0, the residual e_0 - G y
+ *                 formed in FP64 from FP64 weights and monomials; converges
+ *                 to the FP64 result (one or two steps, up to four for
+ *                 ill-conditioned targets; a correction that stops
+ *                 shrinking marks the target SINGULAR). */
 #define PCMS_FP64 0
 #define PCMS_MIXED 1
 #define PCMS_MIXED_REFINE 2
