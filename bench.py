@@ -73,6 +73,47 @@ def load_traffic(kernel_digest):
     return t.get("bytes_per_launch")
 
 
+def operator_leg(torch, pcms, p, src, tgt, vals, rad, steps, dev):
+    """The precomputed transfer operator of the same workload: built once
+    (MIXED_REFINE), then applied to the 8 fields per step -- the coupling
+    pattern of fixed clouds exchanging new fields.  The apply kernel is HBM
+    bound: its roofline counts the operator's 12 bytes per kept source, the
+    per-target count and order (8 bytes), the field values read once and the
+    outputs written once."""
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        op = pcms.Operator(src, tgt, p.degree, rad, p.k_cap, o=pcms.opts(precision=pcms.MIXED_REFINE),
+                           stream=stream)
+        stream.synchronize()
+        build_ms = (time.perf_counter() - t0) * 1e3
+        n_kept, _, _ = op.export(stream=stream)
+        kept = int(n_kept.clamp_min(0).sum())
+        out = torch.empty((p.n_fields, tgt.shape[0]), dtype=torch.float64, device=dev)
+        op.apply(vals, out=out, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            op.apply(vals, out=out, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    m, n_src, nf = tgt.shape[0], src.shape[0], p.n_fields
+    alg_bytes = kept * 12 + m * 8 + n_src * nf * 8 + m * nf * 8
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    log(f"operator: build {build_ms:.2f} ms, width {op.width}, apply {ms:.3f} ms "
+        f"({achieved:.0f} GB/s algorithmic)")
+    op.free()
+    return {
+        "build_ms": build_ms, "apply_ms": ms, "apply_value": m / (ms * 1e-3),
+        "unit": "target pts/s (apply, 8 fields)", "width": op.width, "kept_total": kept,
+        "roofline": {"bound": "hbm", "kernel": "k_op_apply", "achieved": achieved,
+                     "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+                     "alg_bytes_per_launch": alg_bytes},
+    }
+
+
 def batched_leg(torch, pcms, synth, dev, steps):
     """512 transfer problems of uneven size (1k-200k points, log-uniform),
     2-D/3-D, linear/quadratic, 1-16 fields, growing radius: the batched plan
@@ -159,6 +200,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (profiling aid)")
+    ap.add_argument("--no-operator", action="store_true",
+                    help="skip the precomputed-operator leg")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched leg (512 uneven problems in one persistent launch)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -296,6 +339,9 @@ def main():
         result.setdefault("accuracy", {})["max_rel_err_vs_oracle_sample"] = err
         log(f"cpu oracle: {sample} targets in {dt:.1f}s on {threads} threads; "
             f"headline vs oracle max rel err {err:.3e}")
+
+    if not args.no_operator:
+        result["operator"] = operator_leg(torch, pcms, p, src, tgt, vals, rad, args.steps, dev)
 
     if not args.no_batch:
         del head_out, out

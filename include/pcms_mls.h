@@ -173,6 +173,51 @@ pcms_status pcms_mls_transfer_grid(const pcms_grid *grid, const double *src_vals
                                    double *tgt_vals, uint8_t *status);
 
 /* ---------------------------------------------------------------------- */
+/* Precomputed transfer operator: with the source and target clouds fixed, */
+/* the fit of Section 3.2.1, Eq. 1 is linear in the field values,          */
+/* fhat_i = sum_j N_ij f_j with the shape functions                        */
+/* N_ij = w_j p(xi_j)^T (P^T W P + lambda I)^{-1} p(0) of target i's kept  */
+/* sources.  Building N once and applying it to each new set of fields is  */
+/* the coupling pattern of a static discretisation exchanged every step.   */
+/* ---------------------------------------------------------------------- */
+typedef struct pcms_operator pcms_operator;
+
+/* Build the operator of the sources [n_src][dim] and targets [n_tgt][dim]
+ * (same arguments and checks as pcms_mls_transfer, without field values):
+ * the search, the moment assembly and solve of opts.precision, and the
+ * shape functions of every kept source (in FP64).  The operator is library
+ * owned (pcms_operator_free) and holds, per target, at most
+ * pcms_operator_width(op) <= k_cap weights and source indices; the coordinates
+ * are not kept.  status [n_tgt] (may be NULL) and the return code are as for
+ * pcms_mls_transfer; on such a status code *out is still set (failed targets
+ * give NaN when applied). */
+pcms_status pcms_operator_build(const double *src, int64_t n_src, int32_t dim, const double *tgt,
+                                int64_t n_tgt, int32_t basis_degree, const pcms_radius *radius,
+                                int32_t k_cap, const double *inv_scale, const pcms_mls_opts *opts,
+                                pcms_stream_t stream, uint8_t *status, pcms_operator **out);
+
+/* tgt_vals[l][i] = sum over target i's kept sources j of N_ij src_vals[l][j]
+ * for l < n_fields (layouts of pcms_mls_transfer; src_vals of the n_src
+ * sources of the build), NaN for failed targets.  Enqueues one kernel on
+ * `stream` and returns. */
+pcms_status pcms_operator_apply(const pcms_operator *op, const double *src_vals, int32_t n_fields,
+                                pcms_stream_t stream, double *tgt_vals);
+
+/* Copy the operator to DEVICE arrays in original target order: n_kept[i]
+ * (-1 for a failed target) and, for e < n_kept[i], cols[i*stride + e] (source
+ * index) and weights[i*stride + e] (N); the other entries of a row are -1
+ * and 0.  cols and weights may be NULL.  Entries come in search order, not
+ * sorted by source index. */
+pcms_status pcms_operator_export(const pcms_operator *op, int32_t stride, pcms_stream_t stream,
+                                 int32_t *n_kept, int32_t *cols, double *weights);
+
+/* Slots per target of the operator (0 for NULL). */
+int32_t pcms_operator_width(const pcms_operator *op);
+
+/* Release the operator (waits for the device first). */
+pcms_status pcms_operator_free(pcms_operator *op);
+
+/* ---------------------------------------------------------------------- */
 /* Batched transfer: many independent problems of uneven size, dimension,  */
 /* degree and field count (each one the operation of pcms_mls_transfer)    */
 /* executed by one persistent kernel from a work queue, with every stage   */

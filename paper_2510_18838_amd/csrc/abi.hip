@@ -461,6 +461,125 @@ pcms_status pcms_mls_transfer_grid(const pcms_grid *grid, const double *src_vals
                            (hipStream_t)stream, tgt_vals, status);
 }
 
+pcms_status pcms_operator_build(const double *src, int64_t n_src, int32_t dim, const double *tgt,
+                                int64_t n_tgt, int32_t basis_degree, const pcms_radius *radius,
+                                int32_t k_cap, const double *inv_scale, const pcms_mls_opts *opts,
+                                pcms_stream_t stream, uint8_t *status, pcms_operator **out)
+{
+    if (!out) return arg_error("out is NULL");
+    *out = nullptr;
+    if (n_src < 1 || n_src >= ((int64_t)1 << 31) / 2) return arg_error("n_src must be in [1, 2^30)");
+    if (!src) return arg_error("src is NULL");
+    // the operator needs no field values: validate as a one-field transfer
+    double *fake = const_cast<double *>(src);   // only checked for NULL
+    pcms_status st = check_transfer_args(n_src, dim, fake, 1, tgt, n_tgt, basis_degree, radius, k_cap,
+                                         opts, fake);
+    if (st != PCMS_OK) return st;
+    if (n_tgt > 0 && !tgt) return arg_error("tgt is required");
+    if ((st = check_scale(inv_scale, dim)) != PCMS_OK) return st;
+    pcms_mls_opts o;
+    pcms_mls_opts_default(&o);
+    if (opts) o = *opts;
+    const bool async = (o.flags & PCMS_ASYNC) != 0;
+    hipStream_t s = (hipStream_t)stream;
+    std::unique_ptr<Operator> op(new (std::nothrow) Operator());
+    if (!op) return PCMS_ERR_NOMEM;
+    op->n_src = n_src;
+    op->n_tgt = n_tgt;
+    // one-shot grid in stream-ordered scratch
+    double cw, ppc;
+    cell_spec(radius, dim, &cw, &ppc);
+    Grid g{};
+    g.dim = dim;
+    g.n_src = n_src;
+    g.n_cells_cap = cells_cap_for(n_src);
+    for (int k = 0; k < kMaxDim; ++k) g.g[k] = (inv_scale && k < dim) ? inv_scale[k] : 1.0;
+    PCMS_HIP(hipGetDevice(&g.device));
+    LaunchSpec ls{&g, tgt, nullptr, n_tgt, *radius, k_cap, o.block, nullptr};
+    op->width = operator_width(ls);
+    const size_t nt = (size_t)std::max<int64_t>(n_tgt, 1);
+    const size_t o_n = 256 + ((sizeof(int) * nt + 255) & ~(size_t)255);
+    const size_t o_c = o_n + ((sizeof(int32_t) * nt + 255) & ~(size_t)255);
+    const size_t o_w = o_c + ((sizeof(int32_t) * nt * op->width + 255) & ~(size_t)255);
+    const size_t bytes = o_w + sizeof(double) * nt * op->width;
+    hipError_t he = hipMalloc(&op->mem, bytes);
+    if (he != hipSuccess) return hip_fail(he, "hipMalloc(operator)");
+    op->tperm = (int *)((char *)op->mem + 256);
+    op->op_n = (int32_t *)((char *)op->mem + o_n);
+    op->op_c = (int32_t *)((char *)op->mem + o_c);
+    op->op_w = (double *)((char *)op->mem + o_w);
+    auto fail = [&](pcms_status e) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(op->mem);
+        return e;
+    };
+    Scratch sc;
+    sc.s = s;
+    size_t o_cs = 256;
+    size_t o_perm = o_cs + ((sizeof(int) * ((size_t)g.n_cells_cap + 1) + 255) & ~(size_t)255);
+    size_t o_iperm = o_perm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
+    size_t o_spts = o_iperm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
+    size_t o_sum = o_spts + ((sizeof(double) * (size_t)n_src * padded_dim(dim) + 255) & ~(size_t)255);
+    if ((st = scratch_alloc(&sc.p, o_sum + 64, s)) != PCMS_OK) return fail(st);
+    g.params = (GridParams *)sc.p;
+    g.cell_start = (int *)((char *)sc.p + o_cs);
+    g.perm = (int *)((char *)sc.p + o_perm);
+    g.iperm = (int *)((char *)sc.p + o_iperm);
+    g.spts = (double *)((char *)sc.p + o_spts);
+    int32_t *summary = async ? o.summary : (int32_t *)((char *)sc.p + o_sum);
+    if ((st = zero_ints(summary, 4, s)) != PCMS_OK) return fail(st);
+    if ((st = build_grid_device(&g, src, cw, ppc, s)) != PCMS_OK) return fail(st);
+    if (n_tgt > 0) {
+        if ((st = sort_targets(&g, tgt, n_tgt, op->tperm, s)) != PCMS_OK) return fail(st);
+        ls.tperm = op->tperm;
+        ls.summary = summary;
+        if ((st = launch_operator(ls, basis_degree, o.weight, o.precision, o.lambda, op->op_w,
+                                  op->op_c, op->op_n, status, s)) != PCMS_OK)
+            return fail(st);
+    }
+    st = finish(summary, async, s, true);
+    if (st != PCMS_OK && st != PCMS_ERR_UNDERDETERMINED && st != PCMS_ERR_SINGULAR &&
+        st != PCMS_ERR_RADIUS_EXHAUSTED)
+        return fail(st);
+    *out = reinterpret_cast<pcms_operator *>(op.release());
+    return st;
+}
+
+pcms_status pcms_operator_apply(const pcms_operator *op, const double *src_vals, int32_t n_fields,
+                                pcms_stream_t stream, double *tgt_vals)
+{
+    if (!op) return arg_error("operator is NULL");
+    const Operator &o = *reinterpret_cast<const Operator *>(op);
+    if (n_fields < 1) return arg_error("n_fields must be >= 1");
+    if (o.n_tgt > 0 && (!src_vals || !tgt_vals)) return arg_error("src_vals and tgt_vals are required");
+    return operator_apply(o, src_vals, n_fields, tgt_vals, (hipStream_t)stream);
+}
+
+pcms_status pcms_operator_export(const pcms_operator *op, int32_t stride, pcms_stream_t stream,
+                                 int32_t *n_kept, int32_t *cols, double *weights)
+{
+    if (!op) return arg_error("operator is NULL");
+    const Operator &o = *reinterpret_cast<const Operator *>(op);
+    if (stride < 1) return arg_error("stride must be >= 1");
+    if (o.n_tgt > 0 && !n_kept) return arg_error("n_kept is required");
+    return operator_export(o, stride, n_kept, cols, weights, (hipStream_t)stream);
+}
+
+int32_t pcms_operator_width(const pcms_operator *op)
+{
+    return op ? reinterpret_cast<const Operator *>(op)->width : 0;
+}
+
+pcms_status pcms_operator_free(pcms_operator *op)
+{
+    if (!op) return PCMS_OK;
+    Operator *o = reinterpret_cast<Operator *>(op);
+    (void)hipDeviceSynchronize();
+    if (o->mem) (void)hipFree(o->mem);
+    delete o;
+    return PCMS_OK;
+}
+
 void pcms_batch_opts_default(pcms_batch_opts *o)
 {
     if (!o) return;

@@ -166,6 +166,10 @@ struct KArgs {
     int weight;
     double lambda;
     double *out;           // [nf][n_tgt]
+    // operator emission only: [width][n_tgt] weights and source indices, counts
+    double *op_w;
+    int32_t *op_c;
+    int32_t *op_n;
     // outputs
     int32_t *nbr;
     int32_t *n_kept;
@@ -300,7 +304,13 @@ PCMS_HD PCMS_INLINE void neighbour_data(const GridParams &gp, const double (&t)[
 }
 
 // Field transfer of the target at sorted slot i; returns its status.
-template <int D, int P, int PREC, bool UNIT, int G>
+//
+// EMIT (the precomputed transfer operator): instead of evaluating fields,
+// write the shape functions N_e = w_e p_e . y of the kept sources with their
+// original indices, slot e of sorted target i at [e * n_tgt + i], and the
+// kept count at op_n[i] (-1 for a failed target); then fhat = sum_e N_e f_e
+// for any field.
+template <int D, int P, int PREC, bool UNIT, int G, bool EMIT = false>
 PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i, int *L, Grp<G> g)
 {
     constexpr bool MIXED = PREC != PCMS_FP64;
@@ -420,6 +430,34 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
             }
         }
         if (!ok) st |= PCMS_TGT_SINGULAR;
+    }
+    if (EMIT) {
+        if ((st & 0xF) == PCMS_TGT_OK) {
+            const double inv_h = 1.0 / sqrt(r2);
+            const double inv_r2 = 1.0 / r2;
+            for (int e0 = g.q; e0 < n; e0 += G * kApply) {
+                double sb[kApply][D];
+                bool ok[kApply];
+                int pe[kApply];
+                load_neighbours<D, G, kApply>(S, a.spts, e0, n, sb, ok, pe);
+#pragma unroll
+                for (int j = 0; j < kApply; ++j) {
+                    double p[M], w;
+                    neighbour_data<D, P, UNIT, double>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p, w);
+                    double py = 0.0;
+#pragma unroll
+                    for (int u = 0; u < M; ++u) py = __builtin_fma(p[u], y[u], py);
+                    if (ok[j]) {
+                        const size_t at = (size_t)(e0 + j * G) * a.n_tgt + i;
+                        a.op_w[at] = w * py;
+                        a.op_c[at] = a.perm[pe[j]];
+                    }
+                }
+            }
+        }
+        if (g.q == 0) a.op_n[i] = (st & 0xF) == PCMS_TGT_OK ? n : -1;
+        if (a.status && g.q == 0) a.status[ti] = (uint8_t)st;
+        return st;
     }
     if ((st & 0xF) == PCMS_TGT_OK) {
         const double inv_h = 1.0 / sqrt(r2);

@@ -84,6 +84,33 @@ pcms_status launch_transfer(const LaunchSpec &ls, const double *svals, int n_fie
 
 pcms_status zero_ints(int32_t *p, int n, hipStream_t s);
 
+// precomputed transfer operator (mls.hip, op.hip) ----------------------------
+// Library-owned operator: for sorted target i and slot e < op_n[i], weight
+// op_w[e * n_tgt + i] of source op_c[e * n_tgt + i] (original index);
+// op_n[i] = -1 for a failed target; tperm[i] = original index of target i.
+struct Operator {
+    int64_t n_src = 0, n_tgt = 0;
+    int width = 0;
+    void *mem = nullptr;      // one allocation holding the arrays below
+    int *tperm = nullptr;
+    int32_t *op_n = nullptr;
+    int32_t *op_c = nullptr;
+    double *op_w = nullptr;
+};
+// Emits the operator of the targets of ls (sorted by ls.tperm).
+pcms_status launch_operator(const LaunchSpec &ls, int degree, int weight, int precision,
+                            double lambda, double *op_w, int32_t *op_c, int32_t *op_n,
+                            uint8_t *status, hipStream_t s);
+// Slots per target the operator needs (>= every kept count).
+int operator_width(const LaunchSpec &ls);
+// tgt_vals[l][t] = sum_e w f_l[c] over the target's slots, NaN where failed.
+pcms_status operator_apply(const Operator &op, const double *vals, int n_fields, double *out,
+                           hipStream_t s);
+// Copies the operator to caller arrays in original target order:
+// n_kept[t], cols[t * stride + e], weights[t * stride + e] (e < n_kept[t]).
+pcms_status operator_export(const Operator &op, int stride, int32_t *n_kept, int32_t *cols,
+                            double *weights, hipStream_t s);
+
 // batched transfer (batch.hip) -------------------------------------------------
 // Device descriptor of one problem of a batch; its grid, sorted copies and
 // target order are slices of the batch's global arrays at the given offsets.

@@ -27,6 +27,9 @@ template <int D>
 KernelFn transfer_kernel(int degree, int precision, bool unit);
 template <int D>
 KernelFn nbr_kernel(bool unit);
+// The operator-emission variant of transfer_kernel; defined in op_d<D>.hip.
+template <int D>
+KernelFn operator_kernel(int degree, int precision, bool unit);
 
 namespace {
 
@@ -74,12 +77,40 @@ k_transfer(KArgs a)
     add_summary(a.summary, st, active && g.q == 0);
 }
 
+// The same kernel writing the transfer operator instead of field values.
+template <int D, int P, int PREC, bool UNIT, int G>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for<PREC>())))
+k_operator(KArgs a)
+{
+    extern __shared__ int lds[];
+    const int lb = logical_block(a.n_blocks);
+    if (lb >= a.n_blocks) return;
+    const int slot = (int)threadIdx.x / G;
+    const int i = lb * ((int)blockDim.x / G) + slot;
+    const bool active = i < a.n_tgt;   // uniform within a group
+    const Grp<G> g{(int)(threadIdx.x & (G - 1))};
+    int st = 0;
+    if (active) {
+        const GridParams gp = *a.gp;
+        st = xfer_target<D, P, PREC, UNIT, G, true>(a, gp, i, lds + slot * a.stride, g);
+    }
+    add_summary(a.summary, st, active && g.q == 0);
+}
+
 template <int D, int P, bool UNIT>
 KernelFn pick_prec(int precision)
 {
     return precision == PCMS_FP64  ? (KernelFn)k_transfer<D, P, PCMS_FP64, UNIT, kGroup>
          : precision == PCMS_MIXED ? (KernelFn)k_transfer<D, P, PCMS_MIXED, UNIT, kGroup>
                                    : (KernelFn)k_transfer<D, P, PCMS_MIXED_REFINE, UNIT, kGroup>;
+}
+
+template <int D, int P, bool UNIT>
+KernelFn pick_prec_op(int precision)
+{
+    return precision == PCMS_FP64  ? (KernelFn)k_operator<D, P, PCMS_FP64, UNIT, kGroup>
+         : precision == PCMS_MIXED ? (KernelFn)k_operator<D, P, PCMS_MIXED, UNIT, kGroup>
+                                   : (KernelFn)k_operator<D, P, PCMS_MIXED_REFINE, UNIT, kGroup>;
 }
 
 }  // namespace
@@ -102,6 +133,19 @@ KernelFn pick_prec(int precision)
     {                                                                                  \
         return unit ? (KernelFn)k_neighbors<DD, true, kGroup>                          \
                     : (KernelFn)k_neighbors<DD, false, kGroup>;                        \
+    }
+
+#define PCMS_DEFINE_DIM_OPERATOR(DD)                                                   \
+    template <>                                                                        \
+    KernelFn operator_kernel<DD>(int degree, int precision, bool unit)                 \
+    {                                                                                  \
+        if (unit)                                                                      \
+            return degree == 0 ? pick_prec_op<DD, 0, true>(precision)                  \
+                 : degree == 1 ? pick_prec_op<DD, 1, true>(precision)                  \
+                               : pick_prec_op<DD, 2, true>(precision);                 \
+        return degree == 0 ? pick_prec_op<DD, 0, false>(precision)                     \
+             : degree == 1 ? pick_prec_op<DD, 1, false>(precision)                     \
+                           : pick_prec_op<DD, 2, false>(precision);                    \
     }
 
 }  // namespace pcms

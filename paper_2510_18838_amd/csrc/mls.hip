@@ -28,6 +28,18 @@ KernelFn xfer_for(int d, int p, int precision, bool unit)
     return nullptr;
 }
 
+KernelFn op_for(int d, int p, int precision, bool unit)
+{
+    switch (d) {
+    case 1: return operator_kernel<1>(p, precision, unit);
+    case 2: return operator_kernel<2>(p, precision, unit);
+    case 3: return operator_kernel<3>(p, precision, unit);
+    case 4: return operator_kernel<4>(p, precision, unit);
+    case 5: return operator_kernel<5>(p, precision, unit);
+    }
+    return nullptr;
+}
+
 KernelFn nbr_for(int d, bool unit)
 {
     switch (d) {
@@ -134,5 +146,28 @@ pcms_status launch_transfer(const LaunchSpec &ls, const double *svals, int n_fie
     PCMS_HIP(hipGetLastError());
     return PCMS_OK;
 }
+
+pcms_status launch_operator(const LaunchSpec &ls, int degree, int weight, int precision,
+                            double lambda, double *op_w, int32_t *op_c, int32_t *op_n,
+                            uint8_t *status, hipStream_t s)
+{
+    if (ls.n_tgt == 0) return PCMS_OK;
+    const int block = pick_block(ls.block, ls);
+    KArgs a = base_args(ls, block);
+    a.weight = weight;
+    a.lambda = lambda;
+    a.op_w = op_w;
+    a.op_c = op_c;
+    a.op_n = op_n;
+    a.status = status;
+    KernelFn fn = op_for(ls.grid->dim, degree, precision, unit_metric(ls.grid));
+    const int launch = ((a.n_blocks + 7) / 8) * 8;
+    const size_t shm = (size_t)(block / kGroup) * target_stride(ls) * sizeof(int);
+    hipLaunchKernelGGL(fn, dim3(launch), dim3(block), shm, s, a);
+    PCMS_HIP(hipGetLastError());
+    return PCMS_OK;
+}
+
+int operator_width(const LaunchSpec &ls) { return lane_words(ls); }
 
 }  // namespace pcms

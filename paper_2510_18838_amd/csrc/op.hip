@@ -1,0 +1,109 @@
+// Application and export of a precomputed transfer operator (the fit of the
+// PCMS paper, Section 3.2.1, Eq. 1, reduced to its shape functions for fixed
+// source and target clouds: fhat_i = sum_j N_ij f_j for every field).
+//
+// The weights are stored by slot, [slot][sorted target], so a wave's lanes
+// (64 consecutive targets of the processing order) read each slot with one
+// coalesced load; the field values are gathered by source index (field-major
+// caller layout), and the sources of neighbouring targets overlap, which the
+// caches exploit.  Application is bound by HBM traffic: the operator's
+// 12 bytes per kept source, the field values and the outputs.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+namespace pcms {
+
+namespace {
+
+constexpr int kChunk = 8;    // fields per pass over a target's slots
+constexpr int kBatch = 4;    // slots whose loads are issued together
+
+__global__ void __launch_bounds__(256) k_op_apply(const int32_t *__restrict__ opn,
+                                                  const int32_t *__restrict__ opc,
+                                                  const double *__restrict__ opw,
+                                                  const int *__restrict__ tperm, int n_tgt,
+                                                  const double *__restrict__ vals, int64_t n_src,
+                                                  int nf, double *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_tgt) return;
+    const int n = opn[i];
+    const int64_t ti = tperm[i];
+    if (n < 0) {
+        for (int l = 0; l < nf; ++l) out[(int64_t)l * n_tgt + ti] = NAN;
+        return;
+    }
+    for (int l0 = 0; l0 < nf; l0 += kChunk) {
+        double acc[kChunk];
+#pragma unroll
+        for (int l = 0; l < kChunk; ++l) acc[l] = 0.0;
+        for (int e0 = 0; e0 < n; e0 += kBatch) {
+            int c[kBatch];
+            double w[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                const int e = e0 + j;
+                const bool ok = e < n;
+                const int64_t at = (int64_t)(ok ? e : 0) * n_tgt + i;   // slot 0 exists (n >= 1)
+                c[j] = opc[at];
+                w[j] = ok ? opw[at] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+#pragma unroll
+                for (int l = 0; l < kChunk; ++l)
+                    if (l0 + l < nf) acc[l] = __builtin_fma(w[j], vals[(int64_t)(l0 + l) * n_src + c[j]], acc[l]);
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < kChunk; ++l)
+            if (l0 + l < nf) out[(int64_t)(l0 + l) * n_tgt + ti] = acc[l];
+    }
+}
+
+__global__ void k_op_export(const int32_t *__restrict__ opn, const int32_t *__restrict__ opc,
+                            const double *__restrict__ opw, const int *__restrict__ tperm,
+                            int n_tgt, int width, int stride, int32_t *n_kept, int32_t *cols,
+                            double *weights)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_tgt) return;
+    const int n = opn[i];
+    const int64_t ti = tperm[i];
+    n_kept[ti] = n;
+    for (int e = 0; e < width && e < stride; ++e) {
+        const bool ok = e < n;
+        if (cols) cols[ti * stride + e] = ok ? opc[(int64_t)e * n_tgt + i] : -1;
+        if (weights) weights[ti * stride + e] = ok ? opw[(int64_t)e * n_tgt + i] : 0.0;
+    }
+}
+
+}  // namespace
+
+pcms_status operator_apply(const Operator &op, const double *vals, int n_fields, double *out,
+                           hipStream_t s)
+{
+    if (op.n_tgt == 0) return PCMS_OK;
+    const int blocks = (int)((op.n_tgt + 255) / 256);
+    k_op_apply<<<blocks, 256, 0, s>>>(op.op_n, op.op_c, op.op_w, op.tperm, (int)op.n_tgt, vals,
+                                      op.n_src, n_fields, out);
+    PCMS_HIP(hipGetLastError());
+    return PCMS_OK;
+}
+
+pcms_status operator_export(const Operator &op, int stride, int32_t *n_kept, int32_t *cols,
+                            double *weights, hipStream_t s)
+{
+    if (op.n_tgt == 0) return PCMS_OK;
+    const int blocks = (int)((op.n_tgt + 255) / 256);
+    k_op_export<<<blocks, 256, 0, s>>>(op.op_n, op.op_c, op.op_w, op.tperm, (int)op.n_tgt,
+                                       op.width, stride, n_kept, cols, weights);
+    PCMS_HIP(hipGetLastError());
+    return PCMS_OK;
+}
+
+}  // namespace pcms

@@ -35,7 +35,9 @@ PROFILE = 0x2
 EXPORTED = ("pcms_mls_opts_default", "pcms_grid_build", "pcms_grid_free", "pcms_neighbors",
             "pcms_mls_transfer", "pcms_mls_transfer_grid", "pcms_last_phase_ms", "pcms_version",
             "pcms_last_error", "pcms_batch_opts_default", "pcms_batch_plan_create",
-            "pcms_batch_plan_exec", "pcms_batch_plan_free", "pcms_autotune")
+            "pcms_batch_plan_exec", "pcms_batch_plan_free", "pcms_autotune",
+            "pcms_operator_build", "pcms_operator_apply", "pcms_operator_export",
+            "pcms_operator_width", "pcms_operator_free")
 
 
 class PcmsError(RuntimeError):
@@ -120,6 +122,17 @@ def lib() -> ctypes.CDLL:
     L.pcms_autotune.argtypes = [ctypes.POINTER(Problem), i32, ctypes.POINTER(BatchOpts),
                                 ctypes.c_char_p, P, ctypes.POINTER(TuneResult)]
     L.pcms_autotune.restype = i32
+    L.pcms_operator_build.argtypes = [P, i64, i32, P, i64, i32, ctypes.POINTER(Radius), i32, P,
+                                      ctypes.POINTER(MlsOpts), P, P, ctypes.POINTER(P)]
+    L.pcms_operator_build.restype = i32
+    L.pcms_operator_apply.argtypes = [P, P, i32, P, P]
+    L.pcms_operator_apply.restype = i32
+    L.pcms_operator_export.argtypes = [P, i32, P, P, P, P]
+    L.pcms_operator_export.restype = i32
+    L.pcms_operator_width.argtypes = [P]
+    L.pcms_operator_width.restype = i32
+    L.pcms_operator_free.argtypes = [P]
+    L.pcms_operator_free.restype = i32
     _lib = L
     return L
 
@@ -384,3 +397,60 @@ def batch_problem_of(prob, dev, out=None) -> BatchProblem:
     tgt = torch.from_numpy(prob.tgt).to(dev)
     return BatchProblem(src, vals, tgt, prob.degree, radius_of(prob), prob.k_cap,
                         inv_scale=prob.inv_scale, out=out)
+
+
+# --- precomputed transfer operator ----------------------------------------
+
+class Operator:
+    """Owning wrapper of a pcms_operator (shape functions of fixed clouds)."""
+
+    def __init__(self, src: torch.Tensor, tgt: torch.Tensor, basis_degree: int, rad: Radius,
+                 k_cap: int, inv_scale=None, o: Optional[MlsOpts] = None, stream=None,
+                 status: Optional[torch.Tensor] = None, allow_status_errors=True):
+        _dev(src, torch.float64, "src")
+        _dev(tgt, torch.float64, "tgt")
+        n_src, dim = src.shape
+        self.n_src, self.n_tgt, self.k_cap = n_src, tgt.shape[0], int(k_cap)
+        self.status = status if status is not None else torch.empty(self.n_tgt, dtype=torch.uint8,
+                                                                    device=tgt.device)
+        keep, g = _host_scale(inv_scale, dim)
+        o = opts() if o is None else o
+        h = ctypes.c_void_p()
+        allow = _STATUS_CODES if allow_status_errors else ()
+        self.code = _check(lib().pcms_operator_build(_ptr(src), n_src, dim, _ptr(tgt), self.n_tgt,
+                                                     int(basis_degree), ctypes.byref(rad),
+                                                     int(k_cap), g, ctypes.byref(o),
+                                                     _stream(stream), _ptr(self.status),
+                                                     ctypes.byref(h)), allow)
+        self.handle = h
+        self.width = lib().pcms_operator_width(h)
+
+    def apply(self, src_vals: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+        _dev(src_vals, torch.float64, "src_vals")
+        vals2 = src_vals if src_vals.dim() == 2 else src_vals.view(1, -1)
+        nf = vals2.shape[0]
+        if out is None:
+            out = torch.empty((nf, self.n_tgt), dtype=torch.float64, device=src_vals.device)
+        _check(lib().pcms_operator_apply(self.handle, _ptr(vals2), nf, _stream(stream), _ptr(out)))
+        return out
+
+    def export(self, stream=None):
+        """(n_kept [n_tgt], cols [n_tgt, k_cap], weights [n_tgt, k_cap]) device tensors."""
+        dev = self.status.device
+        n_kept = torch.empty(self.n_tgt, dtype=torch.int32, device=dev)
+        cols = torch.empty((self.n_tgt, self.k_cap), dtype=torch.int32, device=dev)
+        w = torch.empty((self.n_tgt, self.k_cap), dtype=torch.float64, device=dev)
+        _check(lib().pcms_operator_export(self.handle, self.k_cap, _stream(stream), _ptr(n_kept),
+                                          _ptr(cols), _ptr(w)))
+        return n_kept, cols, w
+
+    def free(self):
+        if getattr(self, "handle", None):
+            lib().pcms_operator_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -273,11 +273,25 @@ void run_xfer(const KArgs &a, const GridParams &gp)
     run_groups<G>(a, [&](int i, int *L, Grp<G> g) { xfer_target<D, P, PREC, UNIT, G>(a, gp, i, L, g); });
 }
 
+template <int D, int P, int PREC, bool UNIT, int G>
+void run_op(const KArgs &a, const GridParams &gp)
+{
+    run_groups<G>(a, [&](int i, int *L, Grp<G> g) {
+        xfer_target<D, P, PREC, UNIT, G, true>(a, gp, i, L, g);
+    });
+}
+
 template <int D, bool UNIT, int G>
 void dispatch_g(int op, const KArgs &a, const GridParams &gp, int degree, int precision)
 {
     if (op == 0) return run_nbr<D, UNIT, G>(a, gp);
 #define X(PP)                                                                  \
+    if (degree == PP && op == 2) {                                             \
+        if (precision == PCMS_MIXED) return run_op<D, PP, PCMS_MIXED, UNIT, G>(a, gp); \
+        if (precision == PCMS_MIXED_REFINE)                                    \
+            return run_op<D, PP, PCMS_MIXED_REFINE, UNIT, G>(a, gp);            \
+        return run_op<D, PP, PCMS_FP64, UNIT, G>(a, gp);                       \
+    }                                                                          \
     if (degree == PP) {                                                        \
         if (precision == PCMS_MIXED) return run_xfer<D, PP, PCMS_MIXED, UNIT, G>(a, gp); \
         if (precision == PCMS_MIXED_REFINE)                                    \
@@ -403,6 +417,12 @@ int main(int argc, char **argv)
     std::vector<int32_t> nbr((size_t)(n_tgt * k_cap), -1), n_kept(n_tgt), n_found(n_tgt);
     std::vector<double> r2(n_tgt);
     std::vector<uint8_t> status(n_tgt);
+    // operator slots [words][n_tgt] (poisoned: unwritten slots are never read)
+    std::vector<double> op_w((size_t)a.words * n_tgt, NAN);
+    std::vector<int32_t> op_c((size_t)a.words * n_tgt, -7), op_n(n_tgt, -9);
+    a.op_w = op_w.data();
+    a.op_c = op_c.data();
+    a.op_n = op_n.data();
     a.out = out.data();
     a.nbr = nbr.data();
     a.n_kept = n_kept.data();
@@ -431,6 +451,22 @@ int main(int argc, char **argv)
         std::fwrite(n_kept.data(), 4, n_kept.size(), o);
         std::fwrite(n_found.data(), 4, n_found.size(), o);
         std::fwrite(r2.data(), 8, r2.size(), o);
+    } else if (op == 2) {
+        // original target order, k_cap slots per target, as the export entry point
+        std::vector<int32_t> nk(n_tgt), cols((size_t)(n_tgt * k_cap), -1);
+        std::vector<double> w((size_t)(n_tgt * k_cap), 0.0);
+        for (int64_t i = 0; i < n_tgt; ++i) {
+            const int64_t ti = tperm[i];
+            const int n = op_n[i];
+            nk[ti] = n;
+            for (int e = 0; e < n; ++e) {
+                cols[ti * k_cap + e] = op_c[(size_t)e * n_tgt + i];
+                w[ti * k_cap + e] = op_w[(size_t)e * n_tgt + i];
+            }
+        }
+        std::fwrite(nk.data(), 4, nk.size(), o);
+        std::fwrite(cols.data(), 4, cols.size(), o);
+        std::fwrite(w.data(), 8, w.size(), o);
     } else {
         std::fwrite(out.data(), 8, out.size(), o);
     }

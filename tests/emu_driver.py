@@ -48,7 +48,8 @@ def _cell_spec(prob):
 
 
 def run(prob, op, precision=0, weight=0, lam=0.0, group=1, tgt=None):
-    """op 0: neighbour lists; op 1: transfer; group: lanes per target (1, as
+    """op 0: neighbour lists; op 1: transfer; op 2: transfer operator (shape
+    functions, original target order); group: lanes per target (1, as
     in the kernels, or 4).  Returns a dict like the GPU helpers."""
     exe = build()
     t = prob.tgt if tgt is None else tgt
@@ -92,6 +93,12 @@ def run(prob, op, precision=0, weight=0, lam=0.0, group=1, tgt=None):
         r2 = take(np.float64, n_tgt)
         st = take(np.uint8, n_tgt)
         return dict(nbr=nbr, n_kept=n_kept, n_found=n_found, r2=r2, status=st)
+    if op == 2:
+        n_kept = take(np.int32, n_tgt)
+        cols = take(np.int32, n_tgt * prob.k_cap).reshape(n_tgt, prob.k_cap)
+        w = take(np.float64, n_tgt * prob.k_cap).reshape(n_tgt, prob.k_cap)
+        st = take(np.uint8, n_tgt)
+        return dict(n_kept=n_kept, cols=cols, weights=w, status=st)
     out = take(np.float64, nf * n_tgt).reshape(nf, n_tgt)
     st = take(np.uint8, n_tgt)
     return dict(out=out, status=st)

@@ -228,3 +228,45 @@ def case_tight_caps(be):
     p.k_cap, p.degree = 1, 0
     check_lists(be, p, "k_cap = 1")
     check_transfer(be, p, "k_cap = 1")
+
+
+def check_operator(be, prob, where, precisions=(FP64, MIXED_REFINE)):
+    """The transfer operator (kept sources and shape functions per target)
+    against the oracle's lists and shape functions N_e = w_e p_e^T G^{-1} e_0:
+    the same sources (bit-exact sets), the weights to the precision's bar
+    relative to the target's largest |N|."""
+    ref = oracle.transfer(prob.src, prob.vals, prob.tgt, prob.degree, want_shape=True,
+                          **oracle.problem_kwargs(prob))
+    ok_ref = (ref["status"] & 0xF) == 0
+    for prec in precisions:
+        r = be.operator(prob, prec)
+        st = r["status"]
+        bad = np.nonzero(st != ref["status"])[0]
+        limit = 1e-11 if prec == FP64 else 1e-5
+        assert all(ref["pivot_ratio"][i] < limit for i in bad), \
+            f"{where}: status differs at {bad[:5]}"
+        valid = ok_ref & (st == ref["status"])
+        assert (r["n_kept"][(st & 0xF) != 0] == -1).all(), f"{where}: failed targets not marked"
+        worst = 0.0
+        for i in np.nonzero(valid)[0]:
+            n = ref["n_kept"][i]
+            assert r["n_kept"][i] == n, f"{where}: target {i} keeps {r['n_kept'][i]} vs {n}"
+            order = np.argsort(r["cols"][i, :n], kind="stable")
+            cols, w = r["cols"][i, :n][order], r["weights"][i, :n][order]
+            assert np.array_equal(cols, ref["nbr"][i, :n]), f"{where}: target {i} sources differ"
+            wr = ref["shape"][i, :n]
+            kappa = 1.0 / max(ref["pivot_ratio"][i], 1e-300)
+            dev = np.abs(w - wr).max() / np.abs(wr).max()
+            bound = TOL[prec] + COND[prec] * kappa
+            assert dev <= bound, f"{where}: target {i} shape functions off by {dev:.3e} > {bound:.3e}"
+            worst = max(worst, dev)
+        say(f"{where} precision={prec}: operator max rel dev {worst:.3e} over {int(valid.sum())} targets")
+
+
+def case_operator(be):
+    check_operator(be, synth.c1(), "operator c1")
+    check_operator(be, synth.uniform_problem(51, 4000, 700, 3, 2, synth.KNN, n_fields=1, k=30,
+                                             k_cap=40), "operator 3-D kNN")
+    check_operator(be, synth.uniform_problem(52, 3000, 500, 2, 2, synth.GROW, n_fields=1,
+                                             radius=0.02, n_min=12, k_cap=24,
+                                             inv_scale=[1.0, 3.0]), "operator 2-D grow, metric")

@@ -160,3 +160,24 @@ def test_batch_plan_rejects_bad_options():
     L = pcms.lib()
     assert L.pcms_batch_plan_exec(None, None, None) == pcms.PCMS_ERR_ARG
     assert L.pcms_batch_plan_free(None) == pcms.PCMS_OK
+
+
+@needs_lib
+def test_operator_argument_checks():
+    L = pcms.lib()
+    h = ctypes.c_void_p()
+    r = pcms.radius(pcms.RADIUS_FIXED, r=0.1)
+    o = pcms.opts()
+    build = lambda **kw: L.pcms_operator_build(
+        kw.get("src", FAKE), kw.get("n_src", 100), kw.get("dim", 2), kw.get("tgt", FAKE),
+        kw.get("n_tgt", 10), kw.get("degree", 1), ctypes.byref(kw.get("rad", r)),
+        kw.get("k_cap", 32), None, ctypes.byref(o), None, None, ctypes.byref(h))
+    assert build(dim=6) == pcms.PCMS_ERR_ARG and "dim" in pcms.last_error()
+    assert build(src=None) == pcms.PCMS_ERR_ARG
+    assert build(tgt=None) == pcms.PCMS_ERR_ARG
+    assert build(k_cap=2) == pcms.PCMS_ERR_ARG
+    assert build(rad=pcms.radius(pcms.RADIUS_KNN, k=0)) == pcms.PCMS_ERR_ARG
+    assert L.pcms_operator_apply(None, FAKE, 1, None, FAKE) == pcms.PCMS_ERR_ARG
+    assert L.pcms_operator_export(None, 8, None, FAKE, None, None) == pcms.PCMS_ERR_ARG
+    assert L.pcms_operator_width(None) == 0
+    assert L.pcms_operator_free(None) == pcms.PCMS_OK

@@ -22,6 +22,9 @@ class EmuBackend:
         return emu_driver.run(prob, 1, precision=precision, weight=weight, lam=lam,
                               group=self.group)
 
+    def operator(self, prob, precision):
+        return emu_driver.run(prob, 2, precision=precision, group=self.group)
+
 
 BE = EmuBackend(1)    # one lane per target, as the kernels run
 BE4 = EmuBackend(4)   # four cooperating lanes: the group collectives
@@ -80,3 +83,7 @@ def test_emu_lane_groups():
     for i in range(p.tgt.shape[0]):
         n = a["n_kept"][i]
         assert (a["nbr"][i, :n] == b["nbr"][i, :n]).all()
+
+
+def test_emu_operator():
+    C.case_operator(BE)

@@ -1,0 +1,96 @@
+"""The precomputed transfer operator on the GPU: its kept sources and shape
+functions against the oracle's, its application against the one-shot
+transfer (bit-identical in FP64: same shape functions summed in the same
+order) and against exact polynomial reproduction, at small and full size."""
+import numpy as np
+import pytest
+import torch
+
+import parity_cases as C
+from gpu_helpers import DEV, dev, gpu_transfer, say
+from paper_2510_18838_amd import pcms, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def build(prob, precision):
+    return pcms.Operator(dev(prob.src), dev(prob.tgt), prob.degree, pcms.radius_of(prob),
+                         prob.k_cap, inv_scale=prob.inv_scale, o=pcms.opts(precision=precision))
+
+
+class OpBackend:
+    def operator(self, prob, precision):
+        op = build(prob, precision)
+        n_kept, cols, w = op.export()
+        torch.cuda.synchronize()
+        r = dict(n_kept=n_kept.cpu().numpy(), cols=cols.cpu().numpy(), weights=w.cpu().numpy(),
+                 status=op.status.cpu().numpy())
+        op.free()
+        return r
+
+
+def test_operator_against_oracle():
+    C.case_operator(OpBackend())
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c5"])
+def test_apply_matches_transfer(name):
+    prob = C.scaled(name, small=True)
+    for prec in (pcms.FP64, pcms.MIXED_REFINE):
+        op = build(prob, prec)
+        got = op.apply(dev(prob.vals))
+        torch.cuda.synchronize()
+        got = got.cpu().numpy()
+        ref, st, _ = gpu_transfer(prob, prec)
+        assert (op.status.cpu().numpy() == st).all()
+        ok = (st & 0xF) == 0
+        assert np.isnan(got[:, ~ok]).all()
+        if prec == pcms.FP64:
+            assert np.array_equal(got[:, ok], ref[:, ok]), f"{name}: FP64 apply != transfer"
+        else:
+            # the one-shot mixed transfer centres the field values
+            scale = np.abs(ref[:, ok]).max(axis=1, keepdims=True)
+            e = (np.abs(got[:, ok] - ref[:, ok]) / scale).max()
+            say(f"{name} MIXED_REFINE apply vs transfer: {e:.3e}")
+            assert e <= 1e-9
+        op.free()
+
+
+def test_apply_reproduces_polynomials():
+    """Fields that are polynomials of the basis degree are reproduced exactly
+    by the shape functions (at lambda = 0), whatever the weights."""
+    prob = synth.uniform_problem(53, 20000, 3000, 3, 2, synth.KNN, n_fields=1, k=30, k_cap=40)
+    op = build(prob, pcms.FP64)
+    rng = np.random.default_rng(5)
+    x = prob.src
+    c = rng.standard_normal((4, 10))
+    feats = np.stack([np.ones(len(x)), x[:, 0], x[:, 1], x[:, 2], x[:, 0] ** 2, x[:, 0] * x[:, 1],
+                      x[:, 0] * x[:, 2], x[:, 1] ** 2, x[:, 1] * x[:, 2], x[:, 2] ** 2])
+    vals = c @ feats
+    t = prob.tgt
+    tf = np.stack([np.ones(len(t)), t[:, 0], t[:, 1], t[:, 2], t[:, 0] ** 2, t[:, 0] * t[:, 1],
+                   t[:, 0] * t[:, 2], t[:, 1] ** 2, t[:, 1] * t[:, 2], t[:, 2] ** 2])
+    want = c @ tf
+    got = op.apply(dev(vals)).cpu().numpy()
+    ok = (op.status.cpu().numpy() & 0xF) == 0
+    e = np.abs(got[:, ok] - want[:, ok]).max() / np.abs(want[:, ok]).max()
+    say(f"operator polynomial reproduction: {e:.3e}")
+    assert e <= 1e-11
+    op.free()
+
+
+def test_full_c3_operator():
+    prob = synth.c3()
+    op = build(prob, pcms.MIXED_REFINE)
+    vals = dev(prob.vals)
+    got = op.apply(vals)
+    torch.cuda.synchronize()
+    ref, st, _ = gpu_transfer(prob, pcms.MIXED_REFINE)
+    got = got.cpu().numpy()
+    ok = (st & 0xF) == 0
+    assert (op.status.cpu().numpy() == st).all()
+    scale = np.abs(ref[:, ok]).max(axis=1, keepdims=True)
+    e = (np.abs(got[:, ok] - ref[:, ok]) / scale).max()
+    say(f"full c3 operator apply vs transfer: {e:.3e}, width {op.width}")
+    assert e <= 1e-9
+    op.free()
