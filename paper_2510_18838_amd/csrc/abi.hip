@@ -498,13 +498,17 @@ pcms_status pcms_operator_build(const double *src, int64_t n_src, int32_t dim, c
     LaunchSpec ls{&g, tgt, nullptr, n_tgt, *radius, k_cap, o.block, nullptr};
     op->width = operator_width(ls);
     const size_t nt = (size_t)std::max<int64_t>(n_tgt, 1);
-    const size_t o_n = 256 + ((sizeof(int) * nt + 255) & ~(size_t)255);
+    const size_t o_opp = 256 + ((sizeof(int) * nt + 255) & ~(size_t)255);
+    const size_t o_opi = o_opp + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
+    const size_t o_n = o_opi + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
     const size_t o_c = o_n + ((sizeof(int32_t) * nt + 255) & ~(size_t)255);
     const size_t o_w = o_c + ((sizeof(int32_t) * nt * op->width + 255) & ~(size_t)255);
     const size_t bytes = o_w + sizeof(double) * nt * op->width;
     hipError_t he = hipMalloc(&op->mem, bytes);
     if (he != hipSuccess) return hip_fail(he, "hipMalloc(operator)");
     op->tperm = (int *)((char *)op->mem + 256);
+    op->perm = (int *)((char *)op->mem + o_opp);
+    op->iperm = (int *)((char *)op->mem + o_opi);
     op->op_n = (int32_t *)((char *)op->mem + o_n);
     op->op_c = (int32_t *)((char *)op->mem + o_c);
     op->op_w = (double *)((char *)op->mem + o_w);
@@ -529,6 +533,10 @@ pcms_status pcms_operator_build(const double *src, int64_t n_src, int32_t dim, c
     int32_t *summary = async ? o.summary : (int32_t *)((char *)sc.p + o_sum);
     if ((st = zero_ints(summary, 4, s)) != PCMS_OK) return fail(st);
     if ((st = build_grid_device(&g, src, cw, ppc, s)) != PCMS_OK) return fail(st);
+    he = hipMemcpyAsync(op->perm, g.perm, sizeof(int) * (size_t)n_src, hipMemcpyDeviceToDevice, s);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(op->iperm, g.iperm, sizeof(int) * (size_t)n_src, hipMemcpyDeviceToDevice, s);
+    if (he != hipSuccess) return fail(hip_fail(he, "hipMemcpyAsync(operator permutation)"));
     if (n_tgt > 0) {
         if ((st = sort_targets(&g, tgt, n_tgt, op->tperm, s)) != PCMS_OK) return fail(st);
         ls.tperm = op->tperm;

@@ -307,7 +307,7 @@ PCMS_HD PCMS_INLINE void neighbour_data(const GridParams &gp, const double (&t)[
 //
 // EMIT (the precomputed transfer operator): instead of evaluating fields,
 // write the shape functions N_e = w_e p_e . y of the kept sources with their
-// original indices, slot e of sorted target i at [e * n_tgt + i], and the
+// sorted positions, slot e of sorted target i at [e * n_tgt + i], and the
 // kept count at op_n[i] (-1 for a failed target); then fhat = sum_e N_e f_e
 // for any field.
 template <int D, int P, int PREC, bool UNIT, int G, bool EMIT = false>
@@ -450,7 +450,7 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                     if (ok[j]) {
                         const size_t at = (size_t)(e0 + j * G) * a.n_tgt + i;
                         a.op_w[at] = w * py;
-                        a.op_c[at] = a.perm[pe[j]];
+                        a.op_c[at] = pe[j];
                     }
                 }
             }

@@ -86,13 +86,16 @@ pcms_status zero_ints(int32_t *p, int n, hipStream_t s);
 
 // precomputed transfer operator (mls.hip, op.hip) ----------------------------
 // Library-owned operator: for sorted target i and slot e < op_n[i], weight
-// op_w[e * n_tgt + i] of source op_c[e * n_tgt + i] (original index);
-// op_n[i] = -1 for a failed target; tperm[i] = original index of target i.
+// op_w[e * n_tgt + i] of the source at sorted position op_c[e * n_tgt + i];
+// op_n[i] = -1 for a failed target; tperm[i] = original index of target i;
+// perm / iperm map sorted source positions to original indices and back.
 struct Operator {
     int64_t n_src = 0, n_tgt = 0;
     int width = 0;
     void *mem = nullptr;      // one allocation holding the arrays below
     int *tperm = nullptr;
+    int *perm = nullptr;
+    int *iperm = nullptr;
     int32_t *op_n = nullptr;
     int32_t *op_c = nullptr;
     double *op_w = nullptr;
@@ -103,7 +106,9 @@ pcms_status launch_operator(const LaunchSpec &ls, int degree, int weight, int pr
                             uint8_t *status, hipStream_t s);
 // Slots per target the operator needs (>= every kept count).
 int operator_width(const LaunchSpec &ls);
-// tgt_vals[l][t] = sum_e w f_l[c] over the target's slots, NaN where failed.
+// tgt_vals[l][t] = sum_e w f_l[c] over the target's slots, NaN where failed:
+// the fields are first copied into bucket order (records of padded_dim(nf)
+// doubles in stream-ordered scratch), then gathered by sorted position.
 pcms_status operator_apply(const Operator &op, const double *vals, int n_fields, double *out,
                            hipStream_t s);
 // Copies the operator to caller arrays in original target order:

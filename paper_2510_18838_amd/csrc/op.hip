@@ -4,16 +4,20 @@
 //
 // The weights are stored by slot, [slot][sorted target], so a wave's lanes
 // (64 consecutive targets of the processing order) read each slot with one
-// coalesced load; the field values are gathered by source index (field-major
-// caller layout), and the sources of neighbouring targets overlap, which the
-// caches exploit.  Application is bound by HBM traffic: the operator's
-// 12 bytes per kept source, the field values and the outputs.
+// coalesced load.  Each application first copies the caller's field-major
+// values into bucket order (one record of padded_dim(n_fields) doubles per
+// source), then gathers records by sorted position: the kept sources of
+// neighbouring targets are neighbouring records, which the caches exploit.
+// Application is bound by HBM traffic: the operator's 12 bytes per kept
+// source, the field values and the outputs.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 #include <algorithm>
 
+#include "fit.h"
 #include "internal.h"
+#include "launch_common.h"
 
 namespace pcms {
 
@@ -26,11 +30,14 @@ __global__ void __launch_bounds__(256) k_op_apply(const int32_t *__restrict__ op
                                                   const int32_t *__restrict__ opc,
                                                   const double *__restrict__ opw,
                                                   const int *__restrict__ tperm, int n_tgt,
-                                                  const double *__restrict__ vals, int64_t n_src,
-                                                  int nf, double *__restrict__ out)
+                                                  const double *__restrict__ svals, int nf, int nfs,
+                                                  double *__restrict__ out, int n_blocks)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_tgt) return;
+    // XCD-aware: each XCD takes a contiguous range of (spatially sorted)
+    // targets, so its L2 holds the records their neighbours share
+    const int lb = logical_block(n_blocks);
+    const int i = lb * blockDim.x + threadIdx.x;
+    if (lb >= n_blocks || i >= n_tgt) return;
     const int n = opn[i];
     const int64_t ti = tperm[i];
     if (n < 0) {
@@ -52,12 +59,20 @@ __global__ void __launch_bounds__(256) k_op_apply(const int32_t *__restrict__ op
                 c[j] = opc[at];
                 w[j] = ok ? opw[at] : 0.0;
             }
+            double fv[kBatch][kChunk];
 #pragma unroll
             for (int j = 0; j < kBatch; ++j) {
+                const double *row = svals + (int64_t)c[j] * nfs + l0;
 #pragma unroll
-                for (int l = 0; l < kChunk; ++l)
-                    if (l0 + l < nf) acc[l] = __builtin_fma(w[j], vals[(int64_t)(l0 + l) * n_src + c[j]], acc[l]);
+                for (int h = 0; h < kChunk / 2; ++h) {
+                    fv[j][2 * h] = fv[j][2 * h + 1] = 0.0;
+                    if (l0 + 2 * h < nfs) load_pair(row + 2 * h, fv[j][2 * h], fv[j][2 * h + 1]);
+                }
             }
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+#pragma unroll
+                for (int l = 0; l < kChunk; ++l) acc[l] = __builtin_fma(w[j], fv[j][l], acc[l]);
         }
 #pragma unroll
         for (int l = 0; l < kChunk; ++l)
@@ -67,8 +82,8 @@ __global__ void __launch_bounds__(256) k_op_apply(const int32_t *__restrict__ op
 
 __global__ void k_op_export(const int32_t *__restrict__ opn, const int32_t *__restrict__ opc,
                             const double *__restrict__ opw, const int *__restrict__ tperm,
-                            int n_tgt, int width, int stride, int32_t *n_kept, int32_t *cols,
-                            double *weights)
+                            const int *__restrict__ perm, int n_tgt, int width, int stride,
+                            int32_t *n_kept, int32_t *cols, double *weights)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_tgt) return;
@@ -77,7 +92,7 @@ __global__ void k_op_export(const int32_t *__restrict__ opn, const int32_t *__re
     n_kept[ti] = n;
     for (int e = 0; e < width && e < stride; ++e) {
         const bool ok = e < n;
-        if (cols) cols[ti * stride + e] = ok ? opc[(int64_t)e * n_tgt + i] : -1;
+        if (cols) cols[ti * stride + e] = ok ? perm[opc[(int64_t)e * n_tgt + i]] : -1;
         if (weights) weights[ti * stride + e] = ok ? opw[(int64_t)e * n_tgt + i] : 0.0;
     }
 }
@@ -88,10 +103,21 @@ pcms_status operator_apply(const Operator &op, const double *vals, int n_fields,
                            hipStream_t s)
 {
     if (op.n_tgt == 0) return PCMS_OK;
+    const int nfs = padded_dim(n_fields);
+    void *raw = nullptr;
+    pcms_status st = scratch_alloc(&raw, sizeof(double) * (size_t)op.n_src * nfs, s);
+    if (st != PCMS_OK) return st;
+    double *svals = (double *)raw;
+    Grid view{};
+    view.n_src = op.n_src;
+    view.iperm = op.iperm;
+    if ((st = gather_values(&view, vals, n_fields, svals, s)) != PCMS_OK) return st;
     const int blocks = (int)((op.n_tgt + 255) / 256);
-    k_op_apply<<<blocks, 256, 0, s>>>(op.op_n, op.op_c, op.op_w, op.tperm, (int)op.n_tgt, vals,
-                                      op.n_src, n_fields, out);
+    k_op_apply<<<((blocks + 7) / 8) * 8, 256, 0, s>>>(op.op_n, op.op_c, op.op_w, op.tperm,
+                                                      (int)op.n_tgt, svals, n_fields, nfs, out,
+                                                      blocks);
     PCMS_HIP(hipGetLastError());
+    scratch_free(raw, s);
     return PCMS_OK;
 }
 
@@ -100,8 +126,8 @@ pcms_status operator_export(const Operator &op, int stride, int32_t *n_kept, int
 {
     if (op.n_tgt == 0) return PCMS_OK;
     const int blocks = (int)((op.n_tgt + 255) / 256);
-    k_op_export<<<blocks, 256, 0, s>>>(op.op_n, op.op_c, op.op_w, op.tperm, (int)op.n_tgt,
-                                       op.width, stride, n_kept, cols, weights);
+    k_op_export<<<blocks, 256, 0, s>>>(op.op_n, op.op_c, op.op_w, op.tperm, op.perm,
+                                       (int)op.n_tgt, op.width, stride, n_kept, cols, weights);
     PCMS_HIP(hipGetLastError());
     return PCMS_OK;
 }

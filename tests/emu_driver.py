@@ -15,22 +15,36 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "emu", "pcms_emu.cpp")
-EXE = os.path.join(HERE, "emu", "pcms_emu")
-DEPS = [SRC] + [os.path.join(ROOT, "paper_2510_18838_amd", "csrc", f)
+EMU_DIR = os.path.join(HERE, "emu")
+SRC = os.path.join(EMU_DIR, "pcms_emu.cpp")
+EXE = os.path.join(EMU_DIR, "pcms_emu")
+DEPS = [SRC, os.path.join(EMU_DIR, "emu_common.h"), os.path.join(EMU_DIR, "emu_dim.cpp")] + \
+       [os.path.join(ROOT, "paper_2510_18838_amd", "csrc", f)
                 for f in ("device_common.h", "search.h", "fit.h")] + \
        [os.path.join(ROOT, "include", "pcms_mls.h")]
 
 
 def build(force=False) -> str:
+    """Compiles the emulator (the driver and one object per dimension, in
+    parallel) unless it is newer than every source it depends on."""
     if (not force and os.path.exists(EXE)
             and os.path.getmtime(EXE) >= max(os.path.getmtime(d) for d in DEPS)):
         return EXE
-    cmd = ["g++", "-std=c++20", "-O1", "-pthread", "-g", "-fno-omit-frame-pointer",
-           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
-           "-DPCMS_HOST_EMULATION", "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(ROOT, "paper_2510_18838_amd", "csrc"), SRC, "-o", EXE + ".tmp"]
-    subprocess.check_call(cmd)
+    flags = ["g++", "-std=c++20", "-O1", "-pthread", "-g", "-fno-omit-frame-pointer",
+             "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+             "-DPCMS_HOST_EMULATION", "-I", os.path.join(ROOT, "include"),
+             "-I", os.path.join(ROOT, "paper_2510_18838_amd", "csrc"), "-I", EMU_DIR]
+    with tempfile.TemporaryDirectory() as d:
+        jobs, objs = [], []
+        for name, src, extra in [("main", SRC, [])] + [
+                (f"d{k}", os.path.join(EMU_DIR, "emu_dim.cpp"), [f"-DPCMS_EMU_DIM={k}"])
+                for k in range(1, 6)]:
+            obj = os.path.join(d, name + ".o")
+            objs.append(obj)
+            jobs.append(subprocess.Popen(flags + extra + ["-c", src, "-o", obj]))
+        if any(j.wait() != 0 for j in jobs):
+            raise RuntimeError("emulator build failed")
+        subprocess.check_call(flags + objs + ["-o", EXE + ".tmp"])
     os.replace(EXE + ".tmp", EXE)
     return EXE
 
