@@ -114,6 +114,48 @@ def operator_leg(torch, pcms, p, src, tgt, vals, rad, steps, dev):
     }
 
 
+def roundtrip(torch, pcms, synth, dev, iters=(1, 2, 5, 10, 20, 50, 100)):
+    """The paper's round-trip accuracy protocol on point clouds: the field of
+    Eq. 4 on ~307k jittered-lattice points (the vertex count of the paper's
+    mesh) mapped to ~611k points (its element count) and back, repeatedly,
+    with the C4 weight, linear and quadratic bases and three cut-off radii
+    (in units of the source spacing h); the accuracy error of Eq. 2 (L2
+    norm over the source points) after each iteration.  Both transfer
+    operators are built once and applied per iteration."""
+    src, tgt, f = synth.roundtrip_clouds()
+    h = 4.0 / 554
+    s_d, t_d = torch.from_numpy(src).to(dev), torch.from_numpy(tgt).to(dev)
+    fd = torch.from_numpy(f[None, :]).to(dev)
+    rows = []
+    for degree in (1, 2):
+        for rr in (2.5, 3.5, 5.0):
+            rad = pcms.radius(pcms.RADIUS_FIXED, r=rr * h)
+            o = pcms.opts(precision=pcms.FP64, weight=pcms.WEIGHT_C4)
+            t0 = time.perf_counter()
+            fwd = pcms.Operator(s_d, t_d, degree, rad, 128, o=o)
+            back = pcms.Operator(t_d, s_d, degree, rad, 128, o=o)
+            torch.cuda.synchronize()
+            build = (time.perf_counter() - t0) * 1e3
+            g = fd
+            ok = torch.isfinite(back.apply(fwd.apply(g)))[0]
+            err, t0 = {}, time.perf_counter()
+            for it in range(1, max(iters) + 1):
+                g = back.apply(fwd.apply(g))
+                if it in iters:
+                    d = (g[0] - fd[0])[ok]
+                    err[it] = float(torch.linalg.norm(d) / torch.linalg.norm(fd[0][ok]))
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / max(iters)
+            log(f"round trip degree {degree} r={rr}h: " +
+                " ".join(f"{k}:{v:.2e}" for k, v in err.items()))
+            rows.append({"degree": degree, "radius_h": rr, "accuracy_error": err,
+                         "build_ms": build, "ms_per_iteration": ms})
+            fwd.free()
+            back.free()
+    return {"experiment": "round trip, Eq. 4 field, 2-D point clouds", "n_src": int(src.shape[0]),
+            "n_tgt": int(tgt.shape[0]), "weight": "C4", "rows": rows}
+
+
 def batched_leg(torch, pcms, synth, dev, steps):
     """512 transfer problems of uneven size (1k-200k points, log-uniform),
     2-D/3-D, linear/quadratic, 1-16 fields, growing radius: the batched plan
@@ -204,6 +246,9 @@ def main():
                     help="skip the precomputed-operator leg")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched leg (512 uneven problems in one persistent launch)")
+    ap.add_argument("--roundtrip", action="store_true",
+                    help="only run the round-trip accuracy experiment (source -> target -> "
+                         "source iterations of the Eq. 4 field) and print its table as JSON")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes three times "
                          "(calibrates the HBM byte counters against a known traffic)")
@@ -229,6 +274,9 @@ def main():
         return
     pcms.lib()
     dev = torch.device("cuda:0")
+    if args.roundtrip:
+        print(json.dumps(roundtrip(torch, pcms, synth, dev)), flush=True)
+        return
     n = int(4_000_000 * args.scale)
     t0 = time.time()
     p = synth.c3(n_src=n)

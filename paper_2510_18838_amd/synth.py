@@ -279,3 +279,21 @@ def uniform_problem(seed: int, n_src: int, n_tgt: int, dim: int, degree: int, mo
     g = None if inv_scale is None else np.asarray(inv_scale, dtype=np.float64)
     return Problem(f"u{seed}", src, vals, tgt, degree=degree, mode=mode, radius=radius, k=k,
                    n_min=n_min, max_iter=max_iter, k_cap=k_cap, inv_scale=g)
+
+
+def roundtrip_clouds(n_src_side: int = 554, n_tgt_side: int = 782, extent: float = 4.0):
+    """Two 2-D jittered lattices over [0, extent]^2 standing in for a
+    triangle mesh's vertices (n_src_side^2 points) and its element centroids
+    (n_tgt_side^2, about twice as many), with the field of Eq. 4 sampled on
+    the first: f = sin(x) cos(y) + 2."""
+    rs, rt, _, _ = _streams(6)
+
+    def lattice(rng, n):
+        i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        base = np.stack([i.ravel(), j.ravel()], 1).astype(np.float64)
+        return np.ascontiguousarray((base + 0.5 + rng.uniform(-0.3, 0.3, base.shape)) * (extent / n))
+
+    src = lattice(rs, n_src_side)
+    tgt = lattice(rt, n_tgt_side)
+    f = np.sin(src[:, 0]) * np.cos(src[:, 1]) + 2.0
+    return src, tgt, f

@@ -94,3 +94,28 @@ def test_full_c3_operator():
     say(f"full c3 operator apply vs transfer: {e:.3e}, width {op.width}")
     assert e <= 1e-9
     op.free()
+
+
+def test_round_trip_iterations_match_oracle():
+    """Source -> target -> source iterations through two operators (the
+    paper's round-trip accuracy protocol) against the same iterations done
+    with the FP64 oracle, on a small instance."""
+    import oracle
+    src, tgt, f = synth.roundtrip_clouds(40, 57)
+    h = 4.0 / 40
+    kw = dict(mode=synth.FIXED, r=3.5 * h, k_cap=96)
+    ops = [pcms.Operator(dev(a), dev(b), 2, pcms.radius(pcms.RADIUS_FIXED, r=3.5 * h), 96,
+                         o=pcms.opts(precision=pcms.FP64, weight=pcms.WEIGHT_C4))
+           for a, b in ((src, tgt), (tgt, src))]
+    g = dev(f[None, :])
+    ref = f[None, :]
+    for it in range(3):
+        g = ops[1].apply(ops[0].apply(g))
+        ref_t = oracle.transfer(src, ref, tgt, 2, weight_kind=1, **kw)["out"]
+        ref = oracle.transfer(tgt, ref_t, src, 2, weight_kind=1, **kw)["out"]
+        got = g.cpu().numpy()
+        ok = np.isfinite(ref[0])
+        e = np.abs(got[0, ok] - ref[0, ok]).max() / np.abs(ref[0, ok]).max()
+        acc = np.linalg.norm(got[0, ok] - f[ok]) / np.linalg.norm(f[ok])
+        say(f"round trip {it + 1}: vs oracle {e:.3e}, accuracy error {acc:.3e}")
+        assert e <= 1e-10
