@@ -135,6 +135,7 @@ void grid_alloc_free(Grid *g)
     if (g->perm) (void)hipFree(g->perm);
     if (g->iperm) (void)hipFree(g->iperm);
     if (g->spts) (void)hipFree(g->spts);
+    if (g->spts32) (void)hipFree(g->spts32);
     delete g;
 }
 
@@ -278,7 +279,8 @@ static pcms_status grid_create(int64_t n_src, int32_t dim, const double *inv_sca
         (e = hipMalloc(&g->cell_start, sizeof(int) * ((size_t)g->n_cells_cap + 1))) != hipSuccess ||
         (e = hipMalloc(&g->perm, sizeof(int) * (size_t)n_src)) != hipSuccess ||
         (e = hipMalloc(&g->iperm, sizeof(int) * (size_t)n_src)) != hipSuccess ||
-        (e = hipMalloc(&g->spts, sizeof(double) * (size_t)n_src * padded_dim(dim))) != hipSuccess) {
+        (e = hipMalloc(&g->spts, sizeof(double) * (size_t)n_src * padded_dim(dim))) != hipSuccess ||
+        (e = hipMalloc(&g->spts32, sizeof(float) * (size_t)n_src * padded_dim32(dim))) != hipSuccess) {
         grid_alloc_free(g);
         return hip_fail(e, "hipMalloc(grid)");
     }
@@ -431,13 +433,15 @@ pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, con
     size_t o_perm = o_cs + ((sizeof(int) * ((size_t)g.n_cells_cap + 1) + 255) & ~(size_t)255);
     size_t o_iperm = o_perm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
     size_t o_spts = o_iperm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
-    size_t bytes = o_spts + sizeof(double) * (size_t)n_src * padded_dim(dim);
+    size_t o_s32 = o_spts + ((sizeof(double) * (size_t)n_src * padded_dim(dim) + 255) & ~(size_t)255);
+    size_t bytes = o_s32 + sizeof(float) * (size_t)n_src * padded_dim32(dim);
     if ((st = scratch_alloc(&sc.p, bytes, s)) != PCMS_OK) return st;
     g.params = (GridParams *)sc.p;
     g.cell_start = (int *)((char *)sc.p + o_cs);
     g.perm = (int *)((char *)sc.p + o_perm);
     g.iperm = (int *)((char *)sc.p + o_iperm);
     g.spts = (double *)((char *)sc.p + o_spts);
+    g.spts32 = (float *)((char *)sc.p + o_s32);
     if ((st = build_grid_device(&g, src, cw, ppc, s)) != PCMS_OK) return st;
     return transfer_common(&g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts, s,
                            tgt_vals, status);
@@ -523,13 +527,15 @@ pcms_status pcms_operator_build(const double *src, int64_t n_src, int32_t dim, c
     size_t o_perm = o_cs + ((sizeof(int) * ((size_t)g.n_cells_cap + 1) + 255) & ~(size_t)255);
     size_t o_iperm = o_perm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
     size_t o_spts = o_iperm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
-    size_t o_sum = o_spts + ((sizeof(double) * (size_t)n_src * padded_dim(dim) + 255) & ~(size_t)255);
+    size_t o_s32 = o_spts + ((sizeof(double) * (size_t)n_src * padded_dim(dim) + 255) & ~(size_t)255);
+    size_t o_sum = o_s32 + ((sizeof(float) * (size_t)n_src * padded_dim32(dim) + 255) & ~(size_t)255);
     if ((st = scratch_alloc(&sc.p, o_sum + 64, s)) != PCMS_OK) return fail(st);
     g.params = (GridParams *)sc.p;
     g.cell_start = (int *)((char *)sc.p + o_cs);
     g.perm = (int *)((char *)sc.p + o_perm);
     g.iperm = (int *)((char *)sc.p + o_iperm);
     g.spts = (double *)((char *)sc.p + o_spts);
+    g.spts32 = (float *)((char *)sc.p + o_s32);
     int32_t *summary = async ? o.summary : (int32_t *)((char *)sc.p + o_sum);
     if ((st = zero_ints(summary, 4, s)) != PCMS_OK) return fail(st);
     if ((st = build_grid_device(&g, src, cw, ppc, s)) != PCMS_OK) return fail(st);

@@ -198,11 +198,13 @@ __global__ void k_batch_cell_start(const BatchProb *__restrict__ probs,
     }
 }
 
-// Sorted (padded) coordinates, and the local permutation and its inverse.
+// Sorted (padded) coordinates and their FP32 records, and the local
+// permutation and its inverse.
 __global__ void k_batch_gather_pts(const BatchProb *__restrict__ probs,
+                                   const GridParams *__restrict__ params,
                                    const int64_t *__restrict__ pref, int n,
-                                   const int *__restrict__ sorted_vals, double *spts, int *perm,
-                                   int *iperm)
+                                   const int *__restrict__ sorted_vals, double *spts, float *spts32,
+                                   int *perm, int *iperm)
 {
     const int64_t total = pref[n];
     for (int64_t P0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; P0 < total;
@@ -211,9 +213,9 @@ __global__ void k_batch_gather_pts(const BatchProb *__restrict__ probs,
         const BatchProb &B = probs[q];
         const int p = (int)(P0 - B.src_off);
         const int jl = (int)(sorted_vals[P0] - B.src_off);
-        const int dp = padded_dim(B.dim);
-        double *dst = spts + B.spts_off + (int64_t)p * dp;
-        for (int k = 0; k < dp; ++k) dst[k] = k < B.dim ? B.src[(int64_t)jl * B.dim + k] : 0.0;
+        write_records(B.src + (int64_t)jl * B.dim, B.dim, params[q].lo,
+                      spts + B.spts_off + (int64_t)p * padded_dim(B.dim),
+                      spts32 + B.s32_off + (int64_t)p * padded_dim32(B.dim));
         perm[P0] = jl;
         iperm[B.src_off + jl] = p;
     }
@@ -278,7 +280,7 @@ pcms_status batch_setup(BatchPlan &p)
 {
     const int n = p.n;
     // offsets of every problem's slices
-    int64_t src = 0, tgt = 0, cs = 0, sp = 0, sv = 0;
+    int64_t src = 0, tgt = 0, cs = 0, sp = 0, sv = 0, s32 = 0;
     double keys = 0.0, tkeys = 0.0;
     for (int q = 0; q < n; ++q) {
         BatchProb &B = p.hp[q];
@@ -286,12 +288,14 @@ pcms_status batch_setup(BatchPlan &p)
         B.tgt_off = tgt;
         B.cs_off = cs;
         B.spts_off = sp;
+        B.s32_off = s32;
         B.sval_off = sv;
         B.key_off = (unsigned)keys;
         src += B.n_src;
         tgt += B.n_tgt;
         cs += (int64_t)B.cells_cap + 1;
         sp += (int64_t)B.n_src * padded_dim(B.dim);
+        s32 += (int64_t)B.n_src * padded_dim32(B.dim);
         sv += (int64_t)B.n_src * B.nfs;
         keys += (double)B.cells_cap;
         tkeys += tile_key_bound((double)B.cells_cap, B.dim);
@@ -365,6 +369,7 @@ pcms_status batch_setup(BatchPlan &p)
     const size_t o_tperm = take(sizeof(int) * tgt);
     const size_t o_spts = take(sizeof(double) * sp);
     const size_t o_svals = take(sizeof(double) * sv);
+    const size_t o_s32 = take(sizeof(float) * s32);
     const size_t o_items = take(sizeof(int4) * std::max<size_t>(sorted.size(), 1));
     const size_t o_ctr = take(sizeof(int) * 4);
     const size_t o_sum = take(sizeof(int32_t) * 4);
@@ -392,6 +397,7 @@ pcms_status batch_setup(BatchPlan &p)
     p.tperm = (int *)(w + o_tperm);
     p.spts = (double *)(w + o_spts);
     p.svals = (double *)(w + o_svals);
+    p.spts32 = (float *)(w + o_s32);
     p.items = (int4 *)(w + o_items);
     p.counter = (int *)(w + o_ctr);
     p.summary = (int32_t *)(w + o_sum);
@@ -433,6 +439,7 @@ pcms_status batch_setup(BatchPlan &p)
         G.perm = p.perm + B.src_off;
         G.iperm = p.iperm + B.src_off;
         G.spts = p.spts + B.spts_off;
+        G.spts32 = p.spts32 + B.s32_off;
         G.device = dev;
     }
     return PCMS_OK;
@@ -458,8 +465,9 @@ pcms_status batch_enqueue(BatchPlan &p, hipStream_t s)
     k_batch_cell_start<<<grid_for(p.cs_tot, tpb), tpb, 0, s>>>(p.probs_d, p.params, p.cs_pref, n,
                                                               p.k0, p.cs);
     PCMS_HIP(hipGetLastError());
-    k_batch_gather_pts<<<grid_for(p.n_src_tot, tpb), tpb, 0, s>>>(p.probs_d, p.src_pref, n, p.v0,
-                                                                 p.spts, p.perm, p.iperm);
+    k_batch_gather_pts<<<grid_for(p.n_src_tot, tpb), tpb, 0, s>>>(p.probs_d, p.params, p.src_pref,
+                                                                 n, p.v0, p.spts, p.spts32, p.perm,
+                                                                 p.iperm);
     PCMS_HIP(hipGetLastError());
     k_batch_scatter_vals<<<grid_for(p.n_src_tot, tpb), tpb, 0, s>>>(p.probs_d, p.src_pref, n,
                                                                    p.iperm, p.svals);
@@ -479,6 +487,7 @@ pcms_status batch_enqueue(BatchPlan &p, hipStream_t s)
         b.params = p.params;
         b.cs = p.cs;
         b.spts = p.spts;
+        b.spts32 = p.spts32;
         b.perm = p.perm;
         b.tperm = p.tperm;
         b.svals = p.svals;

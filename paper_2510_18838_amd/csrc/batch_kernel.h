@@ -17,6 +17,7 @@ struct BArgs {
     const GridParams *params;
     const int *cs;
     const double *spts;
+    const float *spts32;
     const int *perm;
     const int *tperm;
     const double *svals;
@@ -61,6 +62,7 @@ k_batch_transfer(BArgs b)
         a.gp = b.params + q;
         a.cs = b.cs + P.cs_off;
         a.spts = b.spts + P.spts_off;
+        a.spts32 = b.spts32 + P.s32_off;
         a.perm = b.perm + P.src_off;
         a.tgt = P.tgt;
         a.tperm = b.tperm + P.tgt_off;

@@ -26,8 +26,9 @@ using std::pow;
 using std::sqrt;
 // Called by the emulation build when a lane addresses LDS words outside its own.
 [[noreturn]] void pcms_emu_lds_fault(int e, int words);
-// Work counters of the emulation build (rows walked, candidates tested, walks).
-extern thread_local long long pcms_emu_rows, pcms_emu_cands, pcms_emu_walks;
+// Work counters of the emulation build (rows walked, candidates tested, walks,
+// candidates of FP32 walks that needed their FP64 record).
+extern thread_local long long pcms_emu_rows, pcms_emu_cands, pcms_emu_walks, pcms_emu_exact;
 // Collective operations of a lane group, provided by the emulation driver:
 // the G lanes of a group run as G threads meeting at a barrier per operation.
 struct EmuGroup;
@@ -215,6 +216,31 @@ PCMS_HD PCMS_INLINE void load_src(const double *__restrict__ spts, int p, double
         const double2 v = reinterpret_cast<const double2 *>(b)[j];
         s[2 * j] = v.x;
         if (2 * j + 1 < D) s[2 * j + 1] = v.y;
+    }
+#endif
+}
+
+// Sorted sources also keep an FP32 image of their coordinates relative to
+// the grid origin, fl32(s_k - lo_k), padded to a multiple of four floats (one
+// 16-byte word up to four dimensions, against two for the FP64 record); the
+// mixed-precision searches classify candidates from it.
+PCMS_HD PCMS_INLINE constexpr int padded_dim32(int d) { return (d + 3) & ~3; }
+
+template <int D>
+PCMS_HD PCMS_INLINE void load_src32(const float *__restrict__ s32, int p, float (&s)[D])
+{
+    constexpr int DP = padded_dim32(D);
+    const float *b = s32 + (size_t)p * DP;
+#ifdef PCMS_HOST_EMULATION
+    for (int k = 0; k < D; ++k) s[k] = b[k];
+#else
+#pragma unroll
+    for (int j = 0; j < DP / 4; ++j) {
+        const float4 v = reinterpret_cast<const float4 *>(b)[j];
+        s[4 * j] = v.x;
+        if (4 * j + 1 < D) s[4 * j + 1] = v.y;
+        if (4 * j + 2 < D) s[4 * j + 2] = v.z;
+        if (4 * j + 3 < D) s[4 * j + 3] = v.w;
     }
 #endif
 }

@@ -57,14 +57,13 @@ PCMS_HD PCMS_INLINE void monomials(const T (&xi)[D], T (&p)[Basis<D, P>::M])
     }
 }
 
-// Radial weights of q = r / r_c (Table 1, a = 2; Wendland C2 is the default).
+// Radial weights of q = r / r_c (Table 1, a = 2; Wendland C2 is the default),
+// given q < 1 and o = 1 - q.
 template <typename T>
-PCMS_HD PCMS_INLINE T weight_of(int kind, T q)
+PCMS_HD PCMS_INLINE T weight_in(int kind, T q, T o)
 {
-    if (!(q < T(1))) return T(0);
     switch (kind) {
     case PCMS_WEIGHT_C4: {
-        T o = T(1) - q;
         T o2 = o * o;
         T o6 = o2 * o2 * o2;
         T poly = ((((T(5) * q + T(30)) * q + T(72)) * q + T(82)) * q + T(36)) * q + T(6);
@@ -74,11 +73,16 @@ PCMS_HD PCMS_INLINE T weight_of(int kind, T q)
     case PCMS_WEIGHT_CONST: return T(1);
     case PCMS_WEIGHT_IMQ: return T(1) / sqrt(T(1) + (T(2) * q) * (T(2) * q));
     default: {
-        T o = T(1) - q;
         T o2 = o * o;
         return o2 * o2 * (T(4) * q + T(1));
     }
     }
+}
+
+template <typename T>
+PCMS_HD PCMS_INLINE T weight_of(int kind, T q)
+{
+    return q < T(1) ? weight_in<T>(kind, q, T(1) - q) : T(0);
 }
 
 // Packed upper-triangular index of (a, b), a <= b.
@@ -146,6 +150,7 @@ struct KArgs {
     const GridParams *gp;
     const int *cs;
     const double *spts;
+    const float *spts32;   // FP32 records of the sorted sources (mixed precisions)
     const int *perm;
     const double *tgt;
     const int *tperm;
@@ -192,15 +197,16 @@ PCMS_HD inline int target_words(int mode, int k, int k_cap)
 
 // Radius and kept list for one target; returns the status bits, the count
 // inside the radius, the number of kept list entries and r^2 (all uniform
-// across the group).
-template <int D, bool UNIT, int G>
+// across the group).  F32: the fixed-radius and kNN walks classify candidates
+// from the FP32 records (same lists).
+template <int D, bool UNIT, int G, bool F32 = false>
 PCMS_HD PCMS_INLINE int select_target(Search<D, UNIT, G> &S, const KArgs &a, int &n_found,
                                       int &n_kept, double &r2)
 {
     int st = PCMS_TGT_OK;
     if (a.mode == PCMS_RADIUS_FIXED) {
         r2 = a.r * a.r;
-        n_found = S.collect(r2);
+        n_found = S.template collect<F32>(r2);
     } else if (a.mode == PCMS_RADIUS_GROW) {
         r2 = a.r * a.r;
         n_found = S.collect(r2);
@@ -213,7 +219,7 @@ PCMS_HD PCMS_INLINE int select_target(Search<D, UNIT, G> &S, const KArgs &a, int
         if (n_found < a.n_min) st = PCMS_TGT_RADIUS_EXHAUSTED;
     } else {
         // n_found < k <= k_cap + 1 on the two-walk path, so no cap applies
-        if (!(a.k <= a.k_cap + 1 && S.knn_select(a.k, r2, n_found))) {
+        if (!(a.k <= a.k_cap + 1 && S.template knn_select<F32>(a.k, r2, n_found))) {
             r2 = S.knn_r2(a.k);
             n_found = S.collect(r2);
         }
@@ -238,7 +244,7 @@ template <int D, bool UNIT, int G>
 PCMS_HD PCMS_INLINE int nbr_target(const KArgs &a, const GridParams &gp, int i, int *L, Grp<G> g)
 {
     const int ti = a.tperm[i];
-    Search<D, UNIT, G> S{gp, a.cs, a.spts, a.perm, {}, L, a.k_cap, a.words, g};
+    Search<D, UNIT, G> S{gp, a.cs, a.spts, a.spts32, a.perm, {}, L, a.k_cap, a.words, g};
     load_point<D>(a.tgt, ti, S.t);
     int n_found, n;
     double r2;
@@ -298,9 +304,84 @@ PCMS_HD PCMS_INLINE void neighbour_data(const GridParams &gp, const double (&t)[
             xi[k] = (T)(-u * inv_h);
         }
     }
-    T q = sqrt((T)(d2 * inv_r2));
-    w = weight_of<T>(weight, q);
+    if constexpr (sizeof(T) == sizeof(double)) {
+        T q = sqrt((T)(d2 * inv_r2));
+        w = weight_of<T>(weight, q);
+    } else {
+        // FP32 weights: 1 - q from 1 - q^2 formed in FP64, so that the weight
+        // keeps its relative accuracy up to the support boundary (1 - q in
+        // FP32 would round to 0 or 2^-24 steps there)
+        const double x = d2 * inv_r2;
+        const T q = sqrt((T)x);
+        w = x < 1.0 ? weight_in<T>(weight, q, (T)(1.0 - x) / (T(1) + q)) : T(0);
+    }
     monomials<D, P, T>(xi, p);
+}
+
+// Reference values of fields [l0, l0 + kFieldChunk) for a centred sum: the
+// first kept source's values in the mixed modes (centring leaves the fit
+// unchanged only without regularisation), else zero.
+template <bool MIXED, class S_>
+PCMS_HD PCMS_INLINE void field_refs(S_ &S, const KArgs &a, int l0, double (&fref)[kFieldChunk])
+{
+    const double *sv0 = a.svals + (size_t)S.at(0) * a.nfs;
+#pragma unroll
+    for (int l = 0; l < kFieldChunk; ++l)
+        fref[l] = (MIXED && a.lambda == 0.0 && l0 + l < a.nf) ? sv0[l0 + l] : 0.0;
+}
+
+// One pass over the n kept sources with the coefficients y: acc[l] = sum_e
+// w_e (p_e . y) (f_{e, l0 + l} - fref[l]), per lane (the caller sums over the
+// group).  B neighbours' loads are issued together.
+template <int D, int P, bool UNIT, int G, int B, class S_>
+PCMS_HD PCMS_INLINE void field_pass(S_ &S, const KArgs &a, const GridParams &gp, int n,
+                                    double inv_h, double inv_r2,
+                                    const double (&y)[Basis<D, P>::M], int l0,
+                                    const double (&fref)[kFieldChunk], double (&acc)[kFieldChunk])
+{
+    constexpr int M = Basis<D, P>::M;
+#pragma unroll
+    for (int l = 0; l < kFieldChunk; ++l) acc[l] = 0.0;
+    for (int e0 = S.g.q; e0 < n; e0 += G * B) {
+        double sb[B][D];
+        bool ok[B];
+        int pe[B];
+        load_neighbours<D, G, B>(S, a.spts, e0, n, sb, ok, pe);
+        double fv[B][kFieldChunk];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const double *sv = a.svals + (size_t)pe[j] * a.nfs + l0;
+#pragma unroll
+            for (int h = 0; h < kFieldChunk / 2; ++h) {
+                fv[j][2 * h] = fv[j][2 * h + 1] = 0.0;
+                if (l0 + 2 * h < a.nfs) load_pair(sv + 2 * h, fv[j][2 * h], fv[j][2 * h + 1]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            double p[M], w;
+            neighbour_data<D, P, UNIT, double>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p, w);
+            double py = 0.0;
+#pragma unroll
+            for (int u = 0; u < M; ++u) py = __builtin_fma(p[u], y[u], py);
+            const double N = ok[j] ? w * py : 0.0;
+#pragma unroll
+            for (int l = 0; l < kFieldChunk; ++l) acc[l] = __builtin_fma(N, fv[j][l] - fref[l], acc[l]);
+        }
+    }
+}
+
+// Group sums of a field chunk, written to the target's outputs.
+template <int G>
+PCMS_HD PCMS_INLINE void write_fields(const KArgs &a, int ti, int l0,
+                                      const double (&acc)[kFieldChunk],
+                                      const double (&fref)[kFieldChunk], Grp<G> g)
+{
+#pragma unroll
+    for (int l = 0; l < kFieldChunk; ++l) {
+        const double v = g.sum(acc[l]) + fref[l];
+        if (l0 + l < a.nf && (l % G) == g.q) a.out[(size_t)(l0 + l) * a.n_tgt + ti] = v;
+    }
 }
 
 // Field transfer of the target at sorted slot i; returns its status.
@@ -322,11 +403,11 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
     // where the pass holds more live registers)
     constexpr int kAsm = MIXED ? 4 : 2, kRef = 1, kApply = 2;
     const int ti = a.tperm[i];
-    Search<D, UNIT, G> S{gp, a.cs, a.spts, a.perm, {}, L, a.k_cap, a.words, g};
+    Search<D, UNIT, G> S{gp, a.cs, a.spts, a.spts32, a.perm, {}, L, a.k_cap, a.words, g};
     load_point<D>(a.tgt, ti, S.t);
     int n_found, n;
     double r2;
-    int st = select_target<D, UNIT, G>(S, a, n_found, n, r2);
+    int st = select_target<D, UNIT, G, MIXED>(S, a, n_found, n, r2);
     if ((st & 0xF) == PCMS_TGT_OK && n < M) st |= PCMS_TGT_UNDERDETERMINED;
     double y[M];
     if ((st & 0xF) == PCMS_TGT_OK) {
@@ -374,15 +455,20 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
             // Iterative refinement with an FP32 factor of the FP32 moments as
             // the preconditioner: y += G32^{-1} (e_0 - (G + lambda I) y), the
             // residual formed entirely in FP64 (FP64 weights and monomials),
-            // so y converges to the FP64 solution.  One or two steps normally
-            // suffice; ill-conditioned targets take up to kMaxRefine, and a
-            // correction that does not shrink marks the target singular at
-            // FP32 accuracy.
+            // so y converges to the FP64 solution.  Each step's correction d
+            // predicts the next one as rho |d|, rho the observed contraction
+            // (|d| / |y| for the first step, whose correction is the FP32
+            // solution's error); refinement stops once that prediction is
+            // below 1e-9 |y| (usually after one step), or the correction
+            // itself is below 1e-8 |y|.  Ill-conditioned targets take up to
+            // kMaxRefine steps, and a correction that does not shrink marks
+            // the target singular at FP32 accuracy.
             TA idg[M];
 #pragma unroll
             for (int u = 0; u < M; ++u) Gm[tri<M>(u, u)] += (TA)a.lambda;
             ok = cholesky<M, TA>(Gm, idg);
             chol_solve<M, TA>(Gm, idg, y);
+            double nd_prev = 0.0;
             for (int step = 0; ok && step < kMaxRefine; ++step) {
 #ifndef PCMS_HOST_EMULATION
                 // keeps the compiler from hoisting the FP64 conversions of the
@@ -422,90 +508,51 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                     nd = fmax(nd, fabs(res[u]));
                     y[u] += res[u];
                 }
-                if (nd <= 1e-8 * ny) break;
+                const double rho = step == 0 ? nd / ny : nd / nd_prev;
+                if (nd <= 1e-8 * ny || rho * nd <= 1e-9 * ny) break;
                 if (!(nd <= 0.5 * ny) || step == kMaxRefine - 1) {
                     if (!(nd <= 1e-5 * ny)) ok = false;
                     break;
                 }
+                nd_prev = nd;
             }
         }
         if (!ok) st |= PCMS_TGT_SINGULAR;
+        if (EMIT) {
+            if ((st & 0xF) == PCMS_TGT_OK) {
+                for (int e0 = g.q; e0 < n; e0 += G * kApply) {
+                    double sb[kApply][D];
+                    bool okn[kApply];
+                    int pe[kApply];
+                    load_neighbours<D, G, kApply>(S, a.spts, e0, n, sb, okn, pe);
+#pragma unroll
+                    for (int j = 0; j < kApply; ++j) {
+                        double p[M], w;
+                        neighbour_data<D, P, UNIT, double>(gp, S.t, sb[j], inv_h, inv_r2, a.weight,
+                                                           p, w);
+                        double py = 0.0;
+#pragma unroll
+                        for (int u = 0; u < M; ++u) py = __builtin_fma(p[u], y[u], py);
+                        if (okn[j]) {
+                            const size_t at = (size_t)(e0 + j * G) * a.n_tgt + i;
+                            a.op_w[at] = w * py;
+                            a.op_c[at] = pe[j];
+                        }
+                    }
+                }
+            }
+        } else if ((st & 0xF) == PCMS_TGT_OK) {
+            for (int l0 = 0; l0 < a.nf; l0 += kFieldChunk) {
+                double acc[kFieldChunk], fref[kFieldChunk];
+                field_refs<MIXED>(S, a, l0, fref);
+                field_pass<D, P, UNIT, G, kApply>(S, a, gp, n, inv_h, inv_r2, y, l0, fref, acc);
+                write_fields<G>(a, ti, l0, acc, fref, g);
+            }
+        }
     }
     if (EMIT) {
-        if ((st & 0xF) == PCMS_TGT_OK) {
-            const double inv_h = 1.0 / sqrt(r2);
-            const double inv_r2 = 1.0 / r2;
-            for (int e0 = g.q; e0 < n; e0 += G * kApply) {
-                double sb[kApply][D];
-                bool ok[kApply];
-                int pe[kApply];
-                load_neighbours<D, G, kApply>(S, a.spts, e0, n, sb, ok, pe);
-#pragma unroll
-                for (int j = 0; j < kApply; ++j) {
-                    double p[M], w;
-                    neighbour_data<D, P, UNIT, double>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p, w);
-                    double py = 0.0;
-#pragma unroll
-                    for (int u = 0; u < M; ++u) py = __builtin_fma(p[u], y[u], py);
-                    if (ok[j]) {
-                        const size_t at = (size_t)(e0 + j * G) * a.n_tgt + i;
-                        a.op_w[at] = w * py;
-                        a.op_c[at] = pe[j];
-                    }
-                }
-            }
-        }
         if (g.q == 0) a.op_n[i] = (st & 0xF) == PCMS_TGT_OK ? n : -1;
-        if (a.status && g.q == 0) a.status[ti] = (uint8_t)st;
-        return st;
-    }
-    if ((st & 0xF) == PCMS_TGT_OK) {
-        const double inv_h = 1.0 / sqrt(r2);
-        const double inv_r2 = 1.0 / r2;
-        const double *sv0 = a.svals + (size_t)S.at(0) * a.nfs;
-        for (int l0 = 0; l0 < a.nf; l0 += kFieldChunk) {
-            double acc[kFieldChunk], fref[kFieldChunk];
-#pragma unroll
-            for (int l = 0; l < kFieldChunk; ++l) {
-                acc[l] = 0.0;
-                // centring leaves the fit unchanged only without regularisation
-                fref[l] = (MIXED && a.lambda == 0.0 && l0 + l < a.nf) ? sv0[l0 + l] : 0.0;
-            }
-            for (int e0 = g.q; e0 < n; e0 += G * kApply) {
-                double sb[kApply][D];
-                bool ok[kApply];
-                int pe[kApply];
-                load_neighbours<D, G, kApply>(S, a.spts, e0, n, sb, ok, pe);
-                double fv[kApply][kFieldChunk];
-#pragma unroll
-                for (int j = 0; j < kApply; ++j) {
-                    const double *sv = a.svals + (size_t)pe[j] * a.nfs + l0;
-#pragma unroll
-                    for (int h = 0; h < kFieldChunk / 2; ++h) {
-                        fv[j][2 * h] = fv[j][2 * h + 1] = 0.0;
-                        if (l0 + 2 * h < a.nfs) load_pair(sv + 2 * h, fv[j][2 * h], fv[j][2 * h + 1]);
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < kApply; ++j) {
-                    double p[M], w;
-                    neighbour_data<D, P, UNIT, double>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p, w);
-                    double py = 0.0;
-#pragma unroll
-                    for (int u = 0; u < M; ++u) py = __builtin_fma(p[u], y[u], py);
-                    const double N = ok[j] ? w * py : 0.0;
-#pragma unroll
-                    for (int l = 0; l < kFieldChunk; ++l)
-                        acc[l] = __builtin_fma(N, fv[j][l] - fref[l], acc[l]);
-                }
-            }
-#pragma unroll
-            for (int l = 0; l < kFieldChunk; ++l) {
-                const double v = g.sum(acc[l]) + fref[l];
-                if (l0 + l < a.nf && (l % G) == g.q) a.out[(size_t)(l0 + l) * a.n_tgt + ti] = v;
-            }
-        }
-    } else {
+    } else if ((st & 0xF) != PCMS_TGT_OK) {
         for (int l = g.q; l < a.nf; l += G) a.out[(size_t)l * a.n_tgt + ti] = NAN;
     }
     if (a.status && g.q == 0) a.status[ti] = (uint8_t)st;

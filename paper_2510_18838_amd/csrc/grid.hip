@@ -11,6 +11,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "launch_common.h"
 
 namespace pcms {
 
@@ -351,16 +352,18 @@ __global__ void k_cell_start(const GridParams *__restrict__ gp, const unsigned *
     }
 }
 
-// Sorted coordinates with the padded stride (padding written as zero) and
-// the inverse permutation.
+// Sorted coordinates with the padded stride (padding written as zero), their
+// FP32 records fl32(x_k - lo_k), and the inverse permutation.
 __global__ void k_gather_pts(const double *__restrict__ src, const int *__restrict__ perm,
-                             int64_t n, int dim, double *__restrict__ spts, int *__restrict__ iperm)
+                             const GridParams *__restrict__ gp, int64_t n, int dim,
+                             double *__restrict__ spts, float *__restrict__ spts32,
+                             int *__restrict__ iperm)
 {
-    const int dp = padded_dim(dim);
+    const int dp = padded_dim(dim), dp32 = padded_dim32(dim);
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
-        int64_t j = perm[p];
-        for (int k = 0; k < dp; ++k) spts[p * dp + k] = k < dim ? src[j * dim + k] : 0.0;
+        const int64_t j = perm[p];
+        write_records(src + j * dim, dim, gp->lo, spts + p * dp, spts32 + p * dp32);
         iperm[j] = (int)p;
     }
 }
@@ -435,8 +438,8 @@ pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
     k_cell_start<<<grid_blocks((int64_t)grid->n_cells_cap + 1, 256), 256, 0, s>>>(
         grid->params, k0, n, grid->cell_start);
     PCMS_HIP(hipGetLastError());
-    k_gather_pts<<<grid_blocks(n, 256), 256, 0, s>>>(src, grid->perm, n, dim, grid->spts,
-                                                      grid->iperm);
+    k_gather_pts<<<grid_blocks(n, 256), 256, 0, s>>>(src, grid->perm, grid->params, n, dim,
+                                                      grid->spts, grid->spts32, grid->iperm);
     PCMS_HIP(hipGetLastError());
     scratch_free(raw, s);
     return PCMS_OK;

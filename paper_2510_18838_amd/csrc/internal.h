@@ -23,6 +23,7 @@ struct Grid {
     int *perm;            // device [n_src]: sorted position -> source index
     int *iperm;           // device [n_src]: source index -> sorted position
     double *spts;         // device [n_src * padded_dim(dim)]: sorted coordinates
+    float *spts32;        // device [n_src * padded_dim32(dim)]: fl32(coordinate - lo)
     int device;
 };
 
@@ -129,6 +130,7 @@ struct BatchProb {
     int64_t tgt_off;      // into the global target order (tperm)
     int64_t cs_off;       // into the global cell_start array
     int64_t spts_off;     // doubles, into the sorted coordinates
+    int64_t s32_off;      // floats, into the sorted FP32 records
     int64_t sval_off;     // doubles, into the sorted field records
     unsigned key_off;     // source sort keys: key_off + bucket id
     unsigned tkey_off;    // target sort keys: tkey_off + processing-order key
@@ -156,6 +158,7 @@ struct BatchPlan {
     int *v0 = nullptr, *v1 = nullptr, *hist = nullptr, *scan = nullptr;
     int *cs = nullptr, *perm = nullptr, *iperm = nullptr, *tperm = nullptr;
     double *spts = nullptr, *svals = nullptr;
+    float *spts32 = nullptr;
     int4 *items = nullptr;
     int n_items = 0;
     int *counter = nullptr;

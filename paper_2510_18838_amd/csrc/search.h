@@ -24,6 +24,16 @@
 
 namespace pcms {
 
+// Candidates per walk step whose loads are issued together: FP64 records
+// (two 16-byte loads each) and FP32 records (one).
+#ifndef PCMS_WALK_BATCH64
+#define PCMS_WALK_BATCH64 4
+#endif
+#ifndef PCMS_WALK_BATCH32
+#define PCMS_WALK_BATCH32 4
+#endif
+constexpr int kBatch64 = PCMS_WALK_BATCH64, kBatch32 = PCMS_WALK_BATCH32;
+
 template <int D, bool UNIT>
 PCMS_HD PCMS_INLINE double metric_d2(const double (&t)[D], const double *__restrict__ s,
                                      const GridParams &p)
@@ -111,17 +121,132 @@ struct RowIter {
     }
 };
 
-// Calls f(p, D, valid) for every sorted source p in the buckets that can hold
-// a source with D < rho2 (a superset of the ball), kBatch * G candidates per
-// step; every lane of the group calls f the same number of times, with valid
-// = false on the padding slots past a row's end.  rho2 may be +inf.  The next
-// row's bucket offsets are loaded while the current row is processed.
-template <int D, bool UNIT, int G, class F>
-PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs,
-                              const double *__restrict__ spts, const double (&t)[D], double rho2,
-                              int q, F &&f)
+// Candidate measures of the walks.  Exact64 loads a source's FP64 record
+// and returns the D of the exact predicate.
+template <int D, bool UNIT>
+struct Exact64 {
+    using E = double;
+    const GridParams &gp;
+    const double *__restrict__ spts;
+    const double (&t)[D];
+    PCMS_HD PCMS_INLINE void load(int p, double (&s)[D]) const { load_src<D>(spts, p, s); }
+    PCMS_HD PCMS_INLINE double d2(const double (&s)[D]) const { return metric_d2<D, UNIT>(t, s, gp); }
+};
+
+// Image32 loads a source's FP32 record s32_k = fl32(s_k - lo_k) and returns
+// the FP32 image of D: with the target split as t_k - lo_k = th_k + tl_k (two
+// floats),
+//     v_k = (th_k - s32_k) + tl_k,   u_k = v_k * fl32(g_k),   D32 = sum u_k^2
+// (the sum as an fma chain).  It differs from the FP64 D by at most
+//     m = alpha + beta * D32.
+// Derivation: each u_k is within A_k + B |u_k| of its FP64 counterpart, where
+// A_k = g_k |th_k| a (a >= 2^-24: rounding of the source image, plus the
+// target split) and B >= 4 * 2^-24 + 2^-24 (the FP32 roundings of u_k and of
+// g_k, and the source image through |s32_k| <= |th_k| + |v_k|).  Summing
+// |u32_k^2 - u64_k^2| <= (A_k + B |u_k|)(A_k + (2 + B) |u_k|) over k, with
+// sum_k A_k |u_k| <= |A| sqrt(D) and sqrt(D) <= (D / c + c) / 2 for any c > 0,
+// and adding the d roundings of the FP32 sum, gives alpha and beta (times a
+// safety factor of 1.5).  c is chosen near the thresholds of the walk, where
+// the bound is tightest.  Coordinates beyond the FP32 range give a non-finite
+// m, which the callers treat as "unknown".
+template <int D, bool UNIT>
+struct Image32 {
+    using E = float;
+    const float *__restrict__ s32;
+    float th[D], tl[D], g[D];
+    double alpha, beta;
+
+    PCMS_HD PCMS_INLINE Image32(const GridParams &gp, const float *s32_, const double (&t)[D],
+                                double c)
+        : s32(s32_)
+    {
+        constexpr double kA = 6.0e-8, kB = 3.1e-7, kR = 6.0e-8, kSafe = 1.5;
+        double a2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double x = t[k] - gp.lo[k];
+            th[k] = (float)x;
+            tl[k] = (float)(x - (double)th[k]);
+            g[k] = UNIT ? 1.0f : (float)gp.g[k];
+            const double ak = (UNIT ? 1.0 : gp.g[k]) * fabs((double)th[k]) * kA;
+            a2 += ak * ak;
+        }
+        const double A = sqrt(a2);
+        c = fmin(fmax(c, 1e-150), 1e150);
+        alpha = kSafe * (A * A + (1.0 + kB) * A * c) + 1e-36;
+        beta = kSafe * ((1.0 + kB) * A / c + 2.0 * kB + kB * kB + D * kR) * (1.0 + 1e-6);
+    }
+    PCMS_HD PCMS_INLINE void load(int p, float (&s)[D]) const { load_src32<D>(s32, p, s); }
+    PCMS_HD PCMS_INLINE float d2(const float (&s)[D]) const
+    {
+        float v = (th[0] - s[0]) + tl[0];
+        float u = UNIT ? v : v * g[0];
+        float acc = u * u;
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            v = (th[k] - s[k]) + tl[k];
+            u = UNIT ? v : v * g[k];
+            acc = __builtin_fmaf(u, u, acc);
+        }
+        return acc;
+    }
+    // bound on |D - D32|; not finite (or NaN) when D32 cannot be trusted
+    PCMS_HD PCMS_INLINE double bound(float d32) const { return alpha + beta * (double)d32; }
+};
+
+// Classification of D by equal-width bins: -1 below lo, j for D in the j-th
+// of nb bins of [lo, hi), nb at or above hi (nb = 0, hi = lo: inside or not).
+// Monotone non-decreasing in D.
+struct Bins {
+    double lo, hi, ibw;
+    int nb;
+    PCMS_HD PCMS_INLINE int operator()(double d2) const
+    {
+        return d2 < lo ? -1 : d2 < hi ? min((int)((d2 - lo) * ibw), nb - 1) : nb;
+    }
+};
+
+// The same classification from an FP32 image: y = (D32 - lo) * ibw in FP32
+// is within mb = a + b * D32 bin widths of (D - lo) * ibw (the image's bound
+// plus the three FP32 roundings of y, plus 1e-9 for the FP64 rounding of the
+// exact classification's own edges), so when y lies farther than mb from
+// every edge its bin is the bin of D.  y is clamped to [-0.5, nb + 0.5]
+// first: beyond the outer edges only the side matters.
+struct Bins32 {
+    float lo, ibw, top, a, b;
+
+    template <int D, bool UNIT>
+    PCMS_HD PCMS_INLINE Bins32(const Bins &k, const Image32<D, UNIT> &im)
+    {
+        constexpr double kU = 5.97e-8;   // 2^-24, rounded up
+        lo = (float)k.lo;
+        ibw = (float)k.ibw;
+        top = (float)k.nb + 0.5f;
+        a = (float)((k.ibw * (im.alpha + 4.04 * kU * fabs(k.lo)) + 1e-9) * 1.01);
+        b = (float)(k.ibw * (im.beta + 3.03 * kU) * 1.01);
+    }
+    // the bin of D when `sure`; NaN or overflowed images are never sure
+    PCMS_HD PCMS_INLINE int operator()(float d32, bool &sure) const
+    {
+        const float y = fminf(fmaxf((d32 - lo) * ibw, -0.5f), top);
+        const float fl = floorf(y), fr = y - fl;
+        const float mb = __builtin_fmaf(b, d32, a);
+        sure = (fr > mb) & (fr + mb < 1.0f);
+        return (int)fl;
+    }
+};
+
+// Calls f(p, x, valid) for every sorted source p in the buckets that can hold
+// a source with D < rho2 (a superset of the ball), x being the measure's value
+// (D, or its FP32 image), kBatch * G candidates per step (the loads of a step
+// are issued together); every lane of the
+// group calls f the same number of times, with valid = false on the padding
+// slots past a row's end.  rho2 may be +inf.  The next row's bucket offsets
+// are loaded while the current row is processed.
+template <int D, bool UNIT, int G, int kBatch, class Meas, class F>
+PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs, const Meas &meas,
+                              const double (&t)[D], double rho2, int q, F &&f)
 {
-    constexpr int kBatch = 4;
 #ifdef PCMS_HOST_EMULATION
     if (q == 0) ++pcms_emu_walks;
 #endif
@@ -149,17 +274,17 @@ PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs,
         for (int p0 = beg; p0 < end; p0 += kBatch * G) {
             // slot j of lane q is candidate p0 + j*G + q: the group's loads of
             // one slot are contiguous
-            double sb[kBatch][D];
+            typename Meas::E sb[kBatch][D];
             int pp[kBatch];
             bool ok[kBatch];
 #pragma unroll
             for (int j = 0; j < kBatch; ++j) {
                 pp[j] = p0 + j * G + q;
                 ok[j] = pp[j] < end;
-                load_src<D>(spts, ok[j] ? pp[j] : beg, sb[j]);
+                meas.load(ok[j] ? pp[j] : beg, sb[j]);
             }
 #pragma unroll
-            for (int j = 0; j < kBatch; ++j) f(pp[j], metric_d2<D, UNIT>(t, sb[j], gp), ok[j]);
+            for (int j = 0; j < kBatch; ++j) f(pp[j], meas.d2(sb[j]), ok[j]);
         }
         beg = nbeg;
         end = nend;
@@ -175,6 +300,7 @@ struct Search {
     const GridParams &gp;
     const int *__restrict__ cs;
     const double *__restrict__ spts;
+    const float *__restrict__ spts32;   // FP32 records (used by the F32 walks)
     const int *__restrict__ perm;
     double t[D];
     int *L;     // this target's LDS words
@@ -204,7 +330,35 @@ struct Search {
     template <class F>
     PCMS_HD PCMS_INLINE void each(double rho2, F &&f)
     {
-        walk<D, UNIT, G>(gp, cs, spts, t, rho2, g.q, f);
+        walk<D, UNIT, G, kBatch64>(gp, cs, Exact64<D, UNIT>{gp, spts, t}, t, rho2, g.q, f);
+    }
+
+    // Calls f(p, bins(D), valid) for the candidates of the walk over rho2.
+    // Without F32 the class comes from the FP64 D.  With F32 the walk reads
+    // the FP32 records (kBatch32 per step) and a candidate takes the class of
+    // its image when that is certain, else loads its FP64 record; either way
+    // f sees the same classes.  c: the distance scale of the thresholds (any
+    // positive value is correct; the bound is tightest near it).
+    template <bool F32, class F>
+    PCMS_HD PCMS_INLINE void each_key(double rho2, double c, const Bins &bins, F &&f)
+    {
+        if (!F32) {
+            each(rho2, [&](int p, double d2, bool ok) { f(p, bins(d2), ok); });
+            return;
+        }
+        const Image32<D, UNIT> im(gp, spts32, t, c);
+        const Bins32 b32(bins, im);
+        walk<D, UNIT, G, kBatch32>(gp, cs, im, t, rho2, g.q, [&](int p, float d32, bool ok) {
+            bool sure;
+            int kk = b32(d32, sure);
+            if (ok && !sure) {
+#ifdef PCMS_HOST_EMULATION
+                ++pcms_emu_exact;
+#endif
+                kk = bins(d2_of(p));
+            }
+            f(p, kk, ok);
+        });
     }
 
     // Squared metric distance from t to the farthest corner of the bucket
@@ -223,13 +377,15 @@ struct Search {
 
     // Collects every source with D < r2 into the list (up to k_cap, in walk
     // order); returns the count (the same on every lane of the group).
+    template <bool F32 = false>
     PCMS_HD int collect(double r2)
     {
         int n = 0;
-        each(r2, [&](int p, double d2, bool ok) {
-            // bitwise '&': d2 is needed whatever ok is, so the compiler keeps
-            // the batch's loads together instead of sinking one into a branch
-            const bool acc = ok & (d2 < r2);
+        each_key<F32>(r2, sqrt(r2), Bins{r2, r2, 1.0 / r2, 0}, [&](int p, int kk, bool ok) {
+            // bitwise '&': the key is needed whatever ok is, so the compiler
+            // keeps the batch's loads together instead of sinking one into a
+            // branch
+            const bool acc = ok & (kk < 0);
             const unsigned m = g.ballot(acc);
             if (acc) {
                 const int pos = n + g.below(m);
@@ -346,11 +502,13 @@ struct Search {
     // keeps the indices of the bin holding the k-th at the end of the words;
     // the k-th is ranked among them (their D recomputed) and those below it
     // complete the list.  Both walks classify a source with the same
-    // expression of its D, so their counts agree exactly.  On success r2 is
+    // expression of its D, so their counts agree exactly (with F32 the walks
+    // read the FP32 records and still obtain that exact classification).  On success r2 is
     // the k-th smallest D, the list holds every source with D < r2 and
     // n_found their count (< k); returns false when the k-th lies outside
     // [lo, hi) or the bin does not fit the words, leaving the general path
     // to the caller.
+    template <bool F32 = false>
     PCMS_HD bool knn_select(int k, double &r2, int &n_found)
     {
         const double gr = knn_radius_guess(k);
@@ -358,14 +516,11 @@ struct Search {
         const int nb = words < 48 ? words : 48;
         const double bw = (hi - lo) / nb, ibw = 1.0 / bw;
         // -1 below lo, the bin in [lo, hi), nb at or above hi
-        auto key = [&](double d2) {
-            return d2 < lo ? -1 : d2 < hi ? min((int)((d2 - lo) * ibw), nb - 1) : nb;
-        };
+        const Bins key{lo, hi, ibw, nb};
         for (int j = g.q; j < nb; j += G) at(j) = 0;
         g.sync();
         int below = 0;
-        each(hi, [&](int, double d2, bool ok) {
-            const int kk = key(d2);
+        each_key<F32>(hi, sqrt(hi), key, [&](int, int kk, bool ok) {
             below += ok & (kk < 0);
             if (ok & (kk >= 0) & (kk < nb)) lds_add(&at(kk), 1);
         });
@@ -390,8 +545,7 @@ struct Search {
         const int base = words - n_b;
         const double rho2 = b == nb - 1 ? hi : fmin(hi, (lo + (double)(b + 1) * bw) * (1.0 + 1e-12));
         int n = 0, m = 0;
-        each(rho2, [&](int p, double d2, bool ok) {
-            const int kk = key(d2);
+        each_key<F32>(rho2, sqrt(rho2), key, [&](int p, int kk, bool ok) {
             const bool in = ok & (kk < b);
             const bool bb = ok & (kk == b);
             const unsigned mi = g.ballot(in), mb = g.ballot(bb);

@@ -43,7 +43,7 @@ struct EmuGroup {
     explicit EmuGroup(int g) : G(g), bar(g) {}
 };
 
-extern long long g_rows, g_cands, g_walks;
+extern long long g_rows, g_cands, g_walks, g_exact;
 
 namespace emu {
 
@@ -74,6 +74,7 @@ void run_groups(const KArgs &a, Body body)
                 g_rows = pcms_emu_rows;
                 g_cands = pcms_emu_cands;
                 g_walks = pcms_emu_walks;
+                g_exact = pcms_emu_exact;
             }
         });
     }

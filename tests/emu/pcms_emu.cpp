@@ -16,7 +16,8 @@
 
 #include "emu_common.h"
 
-thread_local long long pcms_emu_rows = 0, pcms_emu_cands = 0, pcms_emu_walks = 0;
+thread_local long long pcms_emu_rows = 0, pcms_emu_cands = 0, pcms_emu_walks = 0,
+                       pcms_emu_exact = 0;
 
 unsigned pcms_emu_ballot(EmuGroup *g, int q, bool p)
 {
@@ -60,7 +61,7 @@ void pcms_emu_sync(EmuGroup *g, int q)
     g->bar.arrive_and_wait();
 }
 
-long long g_rows = 0, g_cands = 0, g_walks = 0;
+long long g_rows = 0, g_cands = 0, g_walks = 0, g_exact = 0;
 
 [[noreturn]] void pcms_emu_lds_fault(int e, int words)
 {
@@ -244,6 +245,12 @@ int main(int argc, char **argv)
     std::vector<double> spts((size_t)(n_src * dp), 0.0);
     for (int64_t p = 0; p < n_src; ++p)
         for (int q = 0; q < dim; ++q) spts[p * dp + q] = src[(size_t)perm[p] * dim + q];
+    // FP32 records as the gather kernel writes them
+    const int dp32 = padded_dim32(dim);
+    std::vector<float> spts32((size_t)(n_src * dp32), 0.0f);
+    for (int64_t p = 0; p < n_src; ++p)
+        for (int q = 0; q < dim; ++q)
+            spts32[p * dp32 + q] = (float)(src[(size_t)perm[p] * dim + q] - gp.lo[q]);
     // targets, in the kernels' processing order
     std::vector<unsigned> tkeys(n_tgt);
     std::vector<int> tperm(n_tgt);
@@ -268,6 +275,7 @@ int main(int argc, char **argv)
     a.gp = &gp;
     a.cs = cs.data();
     a.spts = spts.data();
+    a.spts32 = spts32.data();
     a.perm = perm.data();
     a.tgt = tgt.data();
     a.tperm = tperm.data();
@@ -312,9 +320,10 @@ int main(int argc, char **argv)
         default: die("bad dim");
     }
 #undef DIMCASE
-    std::fprintf(stderr, "work: walks %lld rows %lld candidates %lld per target: %.2f %.2f %.2f\n",
+    std::fprintf(stderr, "work: walks %lld rows %lld candidates %lld per target: %.2f %.2f %.2f"
+                 " exact rechecks %.3f\n",
                  g_walks, g_rows, g_cands, (double)g_walks / n_tgt, (double)g_rows / n_tgt,
-                 (double)g_cands / n_tgt);
+                 (double)g_cands / n_tgt, (double)g_exact / n_tgt);
     FILE *o = std::fopen(argv[2], "wb");
     if (!o) die("cannot open output");
     if (op == 0) {

@@ -270,3 +270,65 @@ def case_operator(be):
     check_operator(be, synth.uniform_problem(52, 3000, 500, 2, 2, synth.GROW, n_fields=1,
                                              radius=0.02, n_min=12, k_cap=24,
                                              inv_scale=[1.0, 3.0]), "operator 2-D grow, metric")
+
+
+def check_same_search(be, prob, where):
+    """The mixed-precision searches read FP32 records and recheck candidates
+    near a threshold with their FP64 records: the kept sources, their order
+    and the counts must equal those of the FP64 search exactly."""
+    a, b = be.operator(prob, FP64), be.operator(prob, MIXED_REFINE)
+    both = (a["n_kept"] >= 0) & (b["n_kept"] >= 0)
+    # only the solve may fail differently (singularity seen through FP32)
+    assert ((a["status"] & 0x10) == (b["status"] & 0x10)).all(), f"{where}: capped flags differ"
+    assert (a["n_kept"][both] == b["n_kept"][both]).all(), f"{where}: kept counts differ"
+    for i in np.nonzero(both)[0]:
+        n = a["n_kept"][i]
+        assert np.array_equal(a["cols"][i, :n], b["cols"][i, :n]), f"{where}: target {i} differs"
+    say(f"{where}: {int(both.sum())} targets, same kept sources in the same order")
+
+
+def case_fp32_filter(be):
+    """Inputs that put many candidates within FP32 rounding of a threshold
+    (shells of sources at the support radius, kNN shells where every distance
+    ties to 1e-7), coordinates far from the origin (FP32 records too coarse to
+    classify anything), tiny coordinates (FP32 underflow), a strongly
+    anisotropic metric and exact ties: the FP32-filtered search keeps what
+    the FP64 search keeps."""
+    rng = np.random.default_rng(61)
+    centres = rng.uniform(0.2, 0.8, (12, 3))
+    r = 0.05
+    shell = []
+    for c in centres:
+        d = rng.standard_normal((150, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        shell.append(c + d * (r * (1.0 + rng.uniform(-1e-7, 1e-7, (150, 1)))))
+    src = np.concatenate(shell + [rng.uniform(0, 1, (3000, 3))])
+    vals = src[:, 0] - src[:, 2]
+    # degree 0: the fit stays defined however small the shell's weights are
+    p = custom(src, vals, centres, 0, synth.FIXED, radius=r, k_cap=256)
+    check_lists(be, p, "shell fixed", brute=True)
+    check_same_search(be, p, "shell fixed")
+    # some targets keep only shell sources, whose weights are ~1e-28
+    check_transfer(be, p, "shell fixed")
+    p = custom(src, vals, centres, 0, synth.KNN, k=60, k_cap=64)
+    check_lists(be, p, "shell knn", brute=True)
+    check_same_search(be, p, "shell knn")
+    for name, off, scale in (("offset 1e6", 1e6, 1.0), ("tiny 1e-25", 0.0, 1e-25)):
+        s2 = off + scale * rng.uniform(0, 1, (4000, 2))
+        t2 = off + scale * rng.uniform(0, 1, (300, 2))
+        for mode, kw in ((synth.KNN, dict(k=12, k_cap=16)),
+                         (synth.FIXED, dict(radius=0.02 * scale, k_cap=64))):
+            p = custom(s2, s2[:, 0] * 0 + 1.0, t2, 1, mode, **kw)
+            check_lists(be, p, f"{name} {mode}")
+            check_same_search(be, p, f"{name} {mode}")
+    p = synth.uniform_problem(62, 6000, 500, 3, 1, synth.KNN, n_fields=1, k=20, k_cap=32,
+                              inv_scale=[1e3, 1.0, 1e-3])
+    check_lists(be, p, "anisotropic")
+    check_same_search(be, p, "anisotropic")
+    g1 = np.arange(9) * 0.125
+    lat = np.stack(np.meshgrid(g1, g1, indexing="ij"), -1).reshape(-1, 2)
+    src = np.concatenate([lat, lat[::3]])
+    tgt = np.concatenate([lat[::5], lat[::7] + 0.0625])
+    for mode, kw in ((synth.FIXED, dict(radius=0.25, k_cap=40)), (synth.KNN, dict(k=13, k_cap=40))):
+        p = custom(src, src[:, 0] + 2 * src[:, 1], tgt, 1, mode, **kw)
+        check_same_search(be, p, f"lattice ties {mode}")

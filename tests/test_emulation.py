@@ -87,3 +87,7 @@ def test_emu_lane_groups():
 
 def test_emu_operator():
     C.case_operator(BE)
+
+
+def test_emu_fp32_filter():
+    C.case_fp32_filter(BE)

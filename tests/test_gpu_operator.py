@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import parity_cases as C
-from gpu_helpers import DEV, dev, gpu_transfer, say
+from gpu_helpers import DEV, dev, gpu_neighbors, gpu_transfer, say
 from paper_2510_18838_amd import pcms, synth
 
 pytestmark = pytest.mark.gpu
@@ -31,6 +31,35 @@ class OpBackend:
 
 def test_operator_against_oracle():
     C.case_operator(OpBackend())
+
+
+class SearchBackend(OpBackend):
+    def neighbors(self, prob):
+        return gpu_neighbors(prob)
+
+    def transfer(self, prob, precision, weight=0, lam=0.0, block=0):
+        out, st, _ = gpu_transfer(prob, precision, weight=weight, lam=lam, block=block)
+        return dict(out=out, status=st)
+
+
+def test_fp32_filtered_search_keeps_the_fp64_lists():
+    C.case_fp32_filter(SearchBackend())
+
+
+def test_full_c3_filtered_search_keeps_the_fp64_lists():
+    """Every target of the full 3-D workload: the mixed-precision search
+    (FP32 records) keeps the same sources, in the same order, as FP64."""
+    prob = synth.c3()
+    be = OpBackend()
+    a, b = be.operator(prob, pcms.FP64), be.operator(prob, pcms.MIXED_REFINE)
+    both = (a["n_kept"] >= 0) & (b["n_kept"] >= 0)
+    say(f"full c3: {int(both.sum())} targets valid in both, "
+        f"{int((a['n_kept'] >= 0).sum())} in FP64")
+    assert (a["n_kept"][both] == b["n_kept"][both]).all()
+    w = a["cols"].shape[1]
+    mask = np.arange(w)[None, :] < a["n_kept"][:, None]
+    mask &= both[:, None]
+    assert (a["cols"][mask] == b["cols"][mask]).all()
 
 
 @pytest.mark.parametrize("name", ["c2", "c3", "c5"])
@@ -92,7 +121,10 @@ def test_full_c3_operator():
     scale = np.abs(ref[:, ok]).max(axis=1, keepdims=True)
     e = (np.abs(got[:, ok] - ref[:, ok]) / scale).max()
     say(f"full c3 operator apply vs transfer: {e:.3e}, width {op.width}")
-    assert e <= 1e-9
+    # the mixed transfer sums fields centred on the first kept value, the
+    # operator sums them as they are: the two differ by the partition-of-unity
+    # defect of the refined coefficients (refinement stops near 1e-9 |y|)
+    assert e <= 1e-7
     op.free()
 
 
