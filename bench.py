@@ -17,7 +17,13 @@ Prints one JSON line with the contract's fields plus:
                 workload on the host cores
   fp64          the same steps with the plain FP64 path, for the comparison
   accuracy      max relative error of the headline path vs FP64 (all
-                targets) and vs the oracle (the sampled targets)
+                targets) and vs the oracle (the sampled targets), and of the
+                FP64 path vs the oracle
+  statuses      per-target status counts of the headline run
+  n_found_histogram  sources inside the radius, per target, over the first
+                200k targets (a neighbour-list call outside the timed steps)
+  cpu_baseline_1thread  the oracle on one host thread (smaller sample)
+  operator, batched  the precomputed-operator and batched legs
 """
 from __future__ import annotations
 
@@ -313,6 +319,7 @@ def main():
     value = M / (ms / 1e3)
     head_out = out.clone()
     status = st.cpu().numpy()
+    out64 = None
 
     result = {
         "metric": METRIC,
@@ -334,6 +341,11 @@ def main():
             "n_fields": p.n_fields, "precision": args.precision,
         },
         "phases_ms": phases,
+        "statuses": {"ok": int(((status & 0xF) == 0).sum()),
+                     "underdetermined": int(((status & 0xF) == 1).sum()),
+                     "singular": int(((status & 0xF) == 2).sum()),
+                     "radius_exhausted": int(((status & 0xF) == 3).sum()),
+                     "capped": int(((status & 0x10) != 0).sum())},
     }
 
     kernel_ms = phases["search_fit"]
@@ -363,6 +375,17 @@ def main():
         result["accuracy"] = {"max_rel_err_vs_fp64_all_targets": err}
         log(f"fp64 {ms64:.3f} ms/step; headline vs fp64 max rel err {err:.3e}")
 
+    # kept-source counts of a 200k-target subset (outside the timed region)
+    sub = tgt[:min(M, 200000)].contiguous()
+    grid = pcms.pcms_grid_build(src, pts_per_cell=0.7 ** 3 * p.k / (4.0 * np.pi / 3.0))
+    nb = pcms.pcms_neighbors(grid, sub, rad, p.k_cap)
+    torch.cuda.synchronize()
+    counts = np.bincount(nb["n_found"].cpu().numpy().clip(0, 4 * p.k_cap))
+    result["n_found_histogram"] = {"targets": int(sub.shape[0]),
+                                   "counts": {str(i): int(c) for i, c in enumerate(counts) if c}}
+    grid.free()
+    del nb
+
     if not args.no_cpu:
         import oracle
         threads = oracle.max_threads()
@@ -385,6 +408,18 @@ def main():
         err = max(float(np.abs(got[l, ok] - ref["out"][l, ok]).max() / np.abs(ref["out"][l, ok]).max())
                   for l in range(p.n_fields))
         result.setdefault("accuracy", {})["max_rel_err_vs_oracle_sample"] = err
+        if out64 is not None:
+            g64 = out64[:, :sample].cpu().numpy()
+            result["accuracy"]["fp64_max_rel_err_vs_oracle_sample"] = max(
+                float(np.abs(g64[l, ok] - ref["out"][l, ok]).max() / np.abs(ref["out"][l, ok]).max())
+                for l in range(p.n_fields))
+        # the oracle on one thread, on a twentieth of the sample
+        s1 = max(1000, sample // 20)
+        t0 = time.time()
+        oracle.transfer(p.src, p.vals, p.tgt[:s1], p.degree, nthreads=1, **oracle.problem_kwargs(p))
+        dt1 = time.time() - t0
+        result["cpu_baseline_1thread"] = {"value": s1 / dt1, "unit": "target pts/s", "cores": 1,
+                                          "sample": f"the first {s1} targets, {dt1:.1f}s"}
         log(f"cpu oracle: {sample} targets in {dt:.1f}s on {threads} threads; "
             f"headline vs oracle max rel err {err:.3e}")
 

@@ -8,8 +8,8 @@
 // values into bucket order (one record of padded_dim(n_fields) doubles per
 // source), then gathers records by sorted position: the kept sources of
 // neighbouring targets are neighbouring records, which the caches exploit.
-// Application is bound by HBM traffic: the operator's 12 bytes per kept
-// source, the field values and the outputs.
+// The operator's 12 bytes per kept source, the field values and the outputs
+// are the HBM traffic; the record gathers are served mostly by the caches.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -23,9 +23,14 @@ namespace pcms {
 
 namespace {
 
-constexpr int kChunk = 8;    // fields per pass over a target's slots
 constexpr int kBatch = 4;    // slots whose loads are issued together
+constexpr int kPairs = 2;    // field pairs per lane and pass over a target's slots
 
+// L lanes per target: lane q of a target sums the field pairs q, q + L, ...
+// (fields 2p, 2p + 1 are one 16-byte word of the record), so the L lanes of a
+// target read one record's consecutive words in the same instruction and a
+// wave's gather touches 64 / L records' lines instead of 64.
+template <int L>
 __global__ void __launch_bounds__(256) k_op_apply(const int32_t *__restrict__ opn,
                                                   const int32_t *__restrict__ opc,
                                                   const double *__restrict__ opw,
@@ -36,18 +41,23 @@ __global__ void __launch_bounds__(256) k_op_apply(const int32_t *__restrict__ op
     // XCD-aware: each XCD takes a contiguous range of (spatially sorted)
     // targets, so its L2 holds the records their neighbours share
     const int lb = logical_block(n_blocks);
-    const int i = lb * blockDim.x + threadIdx.x;
+    const int gi = lb * blockDim.x + threadIdx.x;
+    const int i = gi / L, q = gi % L;
     if (lb >= n_blocks || i >= n_tgt) return;
     const int n = opn[i];
     const int64_t ti = tperm[i];
+    const int np = nfs / 2;   // field pairs per record
     if (n < 0) {
-        for (int l = 0; l < nf; ++l) out[(int64_t)l * n_tgt + ti] = NAN;
+        for (int l = 2 * q; l < nf; l += 2 * L) {
+            out[(int64_t)l * n_tgt + ti] = NAN;
+            if (l + 1 < nf) out[(int64_t)(l + 1) * n_tgt + ti] = NAN;
+        }
         return;
     }
-    for (int l0 = 0; l0 < nf; l0 += kChunk) {
-        double acc[kChunk];
+    for (int p0 = q; p0 < np; p0 += L * kPairs) {
+        double acc[kPairs][2];
 #pragma unroll
-        for (int l = 0; l < kChunk; ++l) acc[l] = 0.0;
+        for (int h = 0; h < kPairs; ++h) acc[h][0] = acc[h][1] = 0.0;
         for (int e0 = 0; e0 < n; e0 += kBatch) {
             int c[kBatch];
             double w[kBatch];
@@ -59,24 +69,31 @@ __global__ void __launch_bounds__(256) k_op_apply(const int32_t *__restrict__ op
                 c[j] = opc[at];
                 w[j] = ok ? opw[at] : 0.0;
             }
-            double fv[kBatch][kChunk];
+            double fv[kBatch][kPairs][2];
 #pragma unroll
             for (int j = 0; j < kBatch; ++j) {
-                const double *row = svals + (int64_t)c[j] * nfs + l0;
+                const double *row = svals + (int64_t)c[j] * nfs;
 #pragma unroll
-                for (int h = 0; h < kChunk / 2; ++h) {
-                    fv[j][2 * h] = fv[j][2 * h + 1] = 0.0;
-                    if (l0 + 2 * h < nfs) load_pair(row + 2 * h, fv[j][2 * h], fv[j][2 * h + 1]);
+                for (int h = 0; h < kPairs; ++h) {
+                    const int p = p0 + h * L;
+                    fv[j][h][0] = fv[j][h][1] = 0.0;
+                    if (p < np) load_pair(row + 2 * p, fv[j][h][0], fv[j][h][1]);
                 }
             }
 #pragma unroll
             for (int j = 0; j < kBatch; ++j)
 #pragma unroll
-                for (int l = 0; l < kChunk; ++l) acc[l] = __builtin_fma(w[j], fv[j][l], acc[l]);
+                for (int h = 0; h < kPairs; ++h) {
+                    acc[h][0] = __builtin_fma(w[j], fv[j][h][0], acc[h][0]);
+                    acc[h][1] = __builtin_fma(w[j], fv[j][h][1], acc[h][1]);
+                }
         }
 #pragma unroll
-        for (int l = 0; l < kChunk; ++l)
-            if (l0 + l < nf) out[(int64_t)(l0 + l) * n_tgt + ti] = acc[l];
+        for (int h = 0; h < kPairs; ++h) {
+            const int l = 2 * (p0 + h * L);
+            if (l < nf) out[(int64_t)l * n_tgt + ti] = acc[h][0];
+            if (l + 1 < nf) out[(int64_t)(l + 1) * n_tgt + ti] = acc[h][1];
+        }
     }
 }
 
@@ -112,10 +129,19 @@ pcms_status operator_apply(const Operator &op, const double *vals, int n_fields,
     view.n_src = op.n_src;
     view.iperm = op.iperm;
     if ((st = gather_values(&view, vals, n_fields, svals, s)) != PCMS_OK) return st;
-    const int blocks = (int)((op.n_tgt + 255) / 256);
-    k_op_apply<<<((blocks + 7) / 8) * 8, 256, 0, s>>>(op.op_n, op.op_c, op.op_w, op.tperm,
-                                                      (int)op.n_tgt, svals, n_fields, nfs, out,
-                                                      blocks);
+    // lanes per target: one per 16-byte word of a record, at most 4
+    const int lanes = nfs >= 8 ? 4 : nfs >= 4 ? 2 : 1;
+    const int blocks = (int)((op.n_tgt * lanes + 255) / 256);
+    const int padded = ((blocks + 7) / 8) * 8;
+    if (lanes == 4)
+        k_op_apply<4><<<padded, 256, 0, s>>>(op.op_n, op.op_c, op.op_w, op.tperm, (int)op.n_tgt,
+                                             svals, n_fields, nfs, out, blocks);
+    else if (lanes == 2)
+        k_op_apply<2><<<padded, 256, 0, s>>>(op.op_n, op.op_c, op.op_w, op.tperm, (int)op.n_tgt,
+                                             svals, n_fields, nfs, out, blocks);
+    else
+        k_op_apply<1><<<padded, 256, 0, s>>>(op.op_n, op.op_c, op.op_w, op.tperm, (int)op.n_tgt,
+                                             svals, n_fields, nfs, out, blocks);
     PCMS_HIP(hipGetLastError());
     scratch_free(raw, s);
     return PCMS_OK;
