@@ -24,6 +24,8 @@ Prints one JSON line with the contract's fields plus:
                 200k targets (a neighbour-list call outside the timed steps)
   cpu_baseline_1thread  the oracle on one host thread (smaller sample)
   operator, batched  the precomputed-operator and batched legs
+  other_configs  the 2-D lattice, 5-D and small 2-D workloads, FP64 and
+                MIXED_REFINE
 """
 from __future__ import annotations
 
@@ -238,6 +240,57 @@ def batched_leg(torch, pcms, synth, dev, steps):
     }
 
 
+def configs_leg(torch, pcms, synth, dev, steps):
+    """The other single-GPU workloads: the 2-D lattice transfer (1M -> 1M,
+    quadratic, fixed radius 3.5 cells, 4 fields), the 5-D transfer (2M -> 2M,
+    linear, growing radius in a standardising metric, 4 fields) and the small
+    2-D correctness case (2k -> 1.5k, linear, fixed radius): one-shot steps in
+    FP64 and MIXED_REFINE, target points per second and the mixed path's
+    error against FP64 (all targets)."""
+    rows = {}
+    for name, make in (("c1", synth.c1), ("c2", synth.c2), ("c5", synth.c5)):
+        p = make()
+        src, vals, tgt = (torch.from_numpy(x).to(dev) for x in (p.src, p.vals, p.tgt))
+        m = tgt.shape[0]
+        rad = pcms.radius_of(p)
+        row = {"n_src": int(p.src.shape[0]), "n_tgt": int(m), "dim": p.dim,
+               "basis_degree": p.degree, "n_fields": p.n_fields}
+        outs = {}
+        for label, prec in (("fp64", pcms.FP64), ("mixed_refine", pcms.MIXED_REFINE)):
+            out = torch.empty((p.n_fields, m), dtype=torch.float64, device=dev)
+            st = torch.empty(m, dtype=torch.uint8, device=dev)
+            o = pcms.opts(precision=prec, flags=pcms.PROFILE)
+            for _ in range(2):
+                pcms.pcms_mls_transfer(src, vals, tgt, p.degree, rad, p.k_cap,
+                                       inv_scale=p.inv_scale, o=o, out=out, status=st)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            kern = []
+            for _ in range(steps):
+                pcms.pcms_mls_transfer(src, vals, tgt, p.degree, rad, p.k_cap,
+                                       inv_scale=p.inv_scale, o=o, out=out, status=st)
+                kern.append(pcms.last_phase_ms()["search_fit"])
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            row[label] = {"ms_per_step": ms, "value": m / (ms * 1e-3),
+                          "search_fit_ms": float(np.mean(kern))}
+            outs[label] = (out, st)
+        ok = (outs["fp64"][1] & 0xF) == 0
+        ok &= outs["fp64"][1] == outs["mixed_refine"][1]
+        err = 0.0
+        for l in range(p.n_fields):
+            ref = outs["fp64"][0][l][ok]
+            err = max(err, float((outs["mixed_refine"][0][l][ok] - ref).abs().max() /
+                                 ref.abs().max()))
+        row["mixed_refine_max_rel_err_vs_fp64"] = err
+        row["valid_targets"] = int(ok.sum())
+        log(f"{name}: fp64 {row['fp64']['ms_per_step']:.3f} ms, mixed_refine "
+            f"{row['mixed_refine']['ms_per_step']:.3f} ms, err {err:.2e}")
+        rows[name] = row
+        del src, vals, tgt, outs
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +305,8 @@ def main():
                     help="skip the precomputed-operator leg")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched leg (512 uneven problems in one persistent launch)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other single-GPU workloads (2-D lattice, 5-D, small 2-D)")
     ap.add_argument("--roundtrip", action="store_true",
                     help="only run the round-trip accuracy experiment (source -> target -> "
                          "source iterations of the Eq. 4 field) and print its table as JSON")
@@ -429,6 +484,9 @@ def main():
     if not args.no_batch:
         del head_out, out
         result["batched"] = batched_leg(torch, pcms, synth, dev, args.steps)
+
+    if not args.no_configs:
+        result["other_configs"] = configs_leg(torch, pcms, synth, dev, args.steps)
 
     print(json.dumps(result), flush=True)
 

@@ -186,19 +186,22 @@ struct KArgs {
 
 // LDS words of a target: its kept list (at most k_cap entries; in kNN mode
 // with k <= k_cap at most k - 1, since every kept D is below the k-th
-// smallest), which also holds the histogram and buffers of the radius search;
-// kNN keeps 8 more for the bin of the k-th; at least 2.
+// smallest), which also holds the histogram and buffers of the radius search,
+// plus 8 for the bin of the k-th smallest D (kNN) or, where the cap is
+// expected to bind (growing radii, kNN beyond the cap), of the k_cap-th.  A
+// fixed radius keeps k_cap words: its rare capped targets take the general
+// bracketing path.
 PCMS_HD inline int target_words(int mode, int k, int k_cap)
 {
-    int w = k_cap;
-    if (mode == PCMS_RADIUS_KNN && k + 8 < k_cap) w = k + 8;
-    return w < 2 ? 2 : w;
+    if (mode == PCMS_RADIUS_KNN && k + 8 < k_cap) return k + 8;
+    if (mode == PCMS_RADIUS_FIXED) return k_cap < 2 ? 2 : k_cap;
+    return k_cap + 8;
 }
 
 // Radius and kept list for one target; returns the status bits, the count
 // inside the radius, the number of kept list entries and r^2 (all uniform
-// across the group).  F32: the fixed-radius and kNN walks classify candidates
-// from the FP32 records (same lists).
+// across the group).  F32: the walks classify candidates from the FP32
+// records (same lists).
 template <int D, bool UNIT, int G, bool F32 = false>
 PCMS_HD PCMS_INLINE int select_target(Search<D, UNIT, G> &S, const KArgs &a, int &n_found,
                                       int &n_kept, double &r2)
@@ -209,12 +212,12 @@ PCMS_HD PCMS_INLINE int select_target(Search<D, UNIT, G> &S, const KArgs &a, int
         n_found = S.template collect<F32>(r2);
     } else if (a.mode == PCMS_RADIUS_GROW) {
         r2 = a.r * a.r;
-        n_found = S.collect(r2);
+        n_found = S.template collect<F32>(r2);
         int it = 0;
         while (n_found < a.n_min && it < a.max_iter) {
             r2 = 2.0 * r2;
             ++it;
-            n_found = S.collect(r2);
+            n_found = S.template collect<F32>(r2);
         }
         if (n_found < a.n_min) st = PCMS_TGT_RADIUS_EXHAUSTED;
     } else {
@@ -227,7 +230,7 @@ PCMS_HD PCMS_INLINE int select_target(Search<D, UNIT, G> &S, const KArgs &a, int
     n_kept = min(n_found, a.k_cap);
     if (n_found > a.k_cap) {
         st |= PCMS_TGT_CAPPED;
-        n_kept = S.cap_collect(r2);
+        n_kept = S.template cap_collect<F32>(r2);
     }
     return st;
 }
@@ -407,7 +410,8 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
     load_point<D>(a.tgt, ti, S.t);
     int n_found, n;
     double r2;
-    int st = select_target<D, UNIT, G, MIXED>(S, a, n_found, n, r2);
+    // FP32 walks where a point's FP32 record is one 16-byte word
+    int st = select_target<D, UNIT, G, MIXED && D <= 4>(S, a, n_found, n, r2);
     if ((st & 0xF) == PCMS_TGT_OK && n < M) st |= PCMS_TGT_UNDERDETERMINED;
     double y[M];
     if ((st & 0xF) == PCMS_TGT_OK) {

@@ -493,27 +493,38 @@ struct Search {
         return metric_d2<D, UNIT>(t, sb, gp);
     }
 
-    // kNN selection in two walks, for k <= k_cap + 1.  The first walk, over
-    // the ball of radius (1 + 0.3) g (g the bucket-count estimate of the
-    // radius), counts the sources below lo = ((1 - 0.22) g)^2 and histograms
-    // those in [lo, hi = ((1 + 0.3) g)^2) into nb bins of equal width in D
-    // (the target's first nb words serve as the bins).  The second walk
+    // kNN selection in two walks, for k <= k_cap + 1: select_window over the
+    // window [((1 - 0.22) g)^2, ((1 + 0.3) g)^2), g the bucket-count estimate
+    // of the radius.  On success r2 is the k-th smallest D, the list holds
+    // every source with D < r2 and n_found their count (< k); false leaves
+    // the general path to the caller.
+    template <bool F32 = false>
+    PCMS_HD bool knn_select(int k, double &r2, int &n_found)
+    {
+        const double gr = knn_radius_guess(k);
+        return select_window<F32, false>(k, (0.78 * gr) * (0.78 * gr), (1.3 * gr) * (1.3 * gr), r2,
+                                         n_found);
+    }
+
+    // The k-th smallest D in two walks, given a window [lo, hi) expected to
+    // hold it.  The first walk, over the ball D < hi, counts the sources
+    // below lo and histograms those in [lo, hi) into nb bins of equal width
+    // in D (the target's first nb words serve as the bins).  The second walk
     // lists, in walk order, every source of a lower bin (or below lo) and
     // keeps the indices of the bin holding the k-th at the end of the words;
     // the k-th is ranked among them (their D recomputed) and those below it
     // complete the list.  Both walks classify a source with the same
     // expression of its D, so their counts agree exactly (with F32 the walks
-    // read the FP32 records and still obtain that exact classification).  On success r2 is
-    // the k-th smallest D, the list holds every source with D < r2 and
-    // n_found their count (< k); returns false when the k-th lies outside
-    // [lo, hi) or the bin does not fit the words, leaving the general path
-    // to the caller.
-    template <bool F32 = false>
-    PCMS_HD bool knn_select(int k, double &r2, int &n_found)
+    // read the FP32 records and still obtain that exact classification).  On
+    // success v is the k-th smallest D and the list holds every source with
+    // D < v, n their count (< k); with TIES the list is then completed to k
+    // entries with sources at D = v, smallest source index first, and n = k.
+    // Returns false when the k-th lies outside [lo, hi) or its bin does not
+    // fit the words.
+    template <bool F32, bool TIES>
+    PCMS_HD bool select_window(int k, double lo, double hi, double &v, int &n_out)
     {
-        const double gr = knn_radius_guess(k);
-        const double lo = (0.78 * gr) * (0.78 * gr), hi = (1.3 * gr) * (1.3 * gr);
-        const int nb = words < 48 ? words : 48;
+        const int nb = words < 64 ? words : 64;
         const double bw = (hi - lo) / nb, ibw = 1.0 / bw;
         // -1 below lo, the bin in [lo, hi), nb at or above hi
         const Bins key{lo, hi, ibw, nb};
@@ -568,31 +579,65 @@ struct Search {
         for (int a0 = 0; a0 < n_b; a0 += G) {
             const int a = a0 + g.q;
             if (a < n_b) {
-                const double v = d2_of(at(base + a));
+                const double x0 = d2_of(at(base + a));
                 int less = 0, le = 0;
                 for (int j = 0; j < n_b; ++j) {
                     const double x = d2_of(at(base + j));
-                    less += x < v;
-                    le += x <= v;
+                    less += x < x0;
+                    le += x <= x0;
                 }
-                if (less < r && r <= le) ans = v;
+                if (less < r && r <= le) ans = x0;
             }
         }
-        r2 = g.min(ans);
-        // append the bin's sources below r2 in walk order; entry j is read
-        // before position c_b + j (<= base + j) can be written
+        v = g.min(ans);
+        if (TIES) {
+            // the k - (c_b + #(bin entries below v)) sources at D = v of
+            // smallest source index join the list: each round marks the next
+            // one (its word holds ~p until it is appended)
+            int below_v = 0;
+            for (int j0 = 0; j0 < n_b; j0 += G) {
+                const int j = j0 + g.q;
+                below_v += j < n_b && d2_of(at(base + j)) < v;
+            }
+            int prev = -1;
+            for (int need = k - c_b - g.sum(below_v); need > 0; --need) {
+                int best = 0x7fffffff, bj = -1;
+                for (int j0 = 0; j0 < n_b; j0 += G) {
+                    const int j = j0 + g.q;
+                    if (j < n_b) {
+                        const int x = at(base + j);
+                        if (x >= 0) {
+                            const int idx = perm[x];
+                            if (idx > prev && idx < best && d2_of(x) == v) {
+                                best = idx;
+                                bj = j;
+                            }
+                        }
+                    }
+                }
+                const int gb = g.min(best);
+                g.sync();
+                if (best == gb && bj >= 0) at(base + bj) = ~at(base + bj);
+                g.sync();
+                prev = gb;
+            }
+        }
+        // append the bin's sources below v (and the marked ones) in walk
+        // order; entry j is read before position c_b + j (<= base + j) can
+        // be written
         int cnt = c_b;
         for (int j0 = 0; j0 < n_b; j0 += G) {
             const int j = j0 + g.q;
-            const int p = j < n_b ? at(base + j) : 0;
-            const bool take = j < n_b && d2_of(p) < r2;
+            const int x = j < n_b ? at(base + j) : 0;
+            const int p = x < 0 ? ~x : x;
+            const bool take = j < n_b && (x < 0 || d2_of(p) < v);
             const unsigned mt = g.ballot(take);
             g.sync();
             if (take) at(cnt + g.below(mt)) = p;
             cnt += __builtin_popcount(mt);
         }
         g.sync();
-        n_found = cnt;
+        n_out = cnt;
         return true;
     }
 
@@ -717,8 +762,13 @@ struct Search {
     // Keeps the k_cap smallest (D, source index) among D < r2 in the list
     // (called when more than k_cap sources are inside); returns the number of
     // list entries written.
+    template <bool F32 = false>
     PCMS_HD int cap_collect(double r2)
     {
+        // usually two walks: the k_cap-th lies in the window [0, r2)
+        double vw;
+        int nw;
+        if (select_window<F32, true>(k_cap, 0.0, r2, vw, nw)) return nw;
         const double v = kth(k_cap, 0.0, 0, r2, words / 2);
         const double vnext = nextafter(v, INFINITY);
         int n = 0, c_eq = 0;
