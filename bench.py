@@ -202,6 +202,21 @@ def batched_leg(torch, pcms, synth, dev, steps):
     log(f"batched MIXED_REFINE: {ms_b:.3f} ms per batch")
     outs_b = [bp.out.clone() for bp in bps]
     st_b = [bp.status.clone() for bp in bps]
+    # the same batch in FP64 (same knobs), for the precision comparison
+    plan64 = pcms.BatchPlan(bps, pcms.batch_opts(precision=pcms.FP64, block=int(tune.block),
+                                                 cell_factor=float(tune.cell_factor)))
+    with torch.cuda.stream(stream):
+        for _ in range(2):
+            plan64.exec(stream=stream, summary=summary)
+        stream.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan64.exec(stream=stream, summary=summary)
+        e1.record(stream)
+        e1.synchronize()
+    ms_b64 = e0.elapsed_time(e1) / steps
+    plan64.free()
+    log(f"batched FP64: {ms_b64:.3f} ms per batch")
     # the same problems through the one-problem FP64 path
     o64 = pcms.opts(precision=pcms.FP64)
 
@@ -231,6 +246,8 @@ def batched_leg(torch, pcms, synth, dev, steps):
         "n_problems": len(bps), "n_tgt": int(n_tgt),
         "mixed_refine_batched": {"ms": ms_b, "value": n_tgt / (ms_b / 1e3), "unit": "target pts/s",
                                  "launch": "one persistent kernel, HIP graph replay"},
+        "fp64_batched": {"ms": ms_b64, "value": n_tgt / (ms_b64 / 1e3), "unit": "target pts/s",
+                         "launch": "the same plan in FP64"},
         "fp64_unbatched": {"ms": ms_u, "value": n_tgt / (ms_u / 1e3), "unit": "target pts/s",
                            "launch": "one one-shot call per problem"},
         "speedup": ms_u / ms_b,
