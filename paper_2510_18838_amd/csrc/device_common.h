@@ -221,28 +221,18 @@ PCMS_HD PCMS_INLINE void load_src(const double *__restrict__ spts, int p, double
 }
 
 // Sorted sources also keep an FP32 image of their coordinates relative to
-// the grid origin, fl32(s_k - lo_k), padded to a multiple of four floats (one
-// 16-byte word up to four dimensions, against two for the FP64 record); the
-// mixed-precision searches classify candidates from it.
-PCMS_HD PCMS_INLINE constexpr int padded_dim32(int d) { return (d + 3) & ~3; }
+// the grid origin, fl32(s_k - lo_k), packed with no padding (a 3-D point is
+// 12 bytes and loads as one 12-byte word: ten records share a 128-byte line
+// instead of eight); the mixed-precision searches classify candidates from it.
+PCMS_HD PCMS_INLINE constexpr int padded_dim32(int d) { return d; }
 
 template <int D>
 PCMS_HD PCMS_INLINE void load_src32(const float *__restrict__ s32, int p, float (&s)[D])
 {
-    constexpr int DP = padded_dim32(D);
-    const float *b = s32 + (size_t)p * DP;
-#ifdef PCMS_HOST_EMULATION
-    for (int k = 0; k < D; ++k) s[k] = b[k];
-#else
+    // adjacent scalar loads, which the compiler merges into one wide load
+    const float *b = s32 + (size_t)p * D;
 #pragma unroll
-    for (int j = 0; j < DP / 4; ++j) {
-        const float4 v = reinterpret_cast<const float4 *>(b)[j];
-        s[4 * j] = v.x;
-        if (4 * j + 1 < D) s[4 * j + 1] = v.y;
-        if (4 * j + 2 < D) s[4 * j + 2] = v.z;
-        if (4 * j + 3 < D) s[4 * j + 3] = v.w;
-    }
-#endif
+    for (int k = 0; k < D; ++k) s[k] = b[k];
 }
 
 // Two consecutive doubles from a 16-byte aligned address, in one load.

@@ -410,7 +410,7 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
     load_point<D>(a.tgt, ti, S.t);
     int n_found, n;
     double r2;
-    // FP32 walks where a point's FP32 record is one 16-byte word
+    // FP32 walks where a point's FP32 record is one load (at most 16 bytes)
     int st = select_target<D, UNIT, G, MIXED && D <= 4>(S, a, n_found, n, r2);
     if ((st & 0xF) == PCMS_TGT_OK && n < M) st |= PCMS_TGT_UNDERDETERMINED;
     double y[M];

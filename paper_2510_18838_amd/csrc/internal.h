@@ -23,7 +23,7 @@ struct Grid {
     int *perm;            // device [n_src]: sorted position -> source index
     int *iperm;           // device [n_src]: source index -> sorted position
     double *spts;         // device [n_src * padded_dim(dim)]: sorted coordinates
-    float *spts32;        // device [n_src * padded_dim32(dim)]: fl32(coordinate - lo)
+    float *spts32;        // device [n_src * dim]: fl32(coordinate - lo), packed
     int device;
 };
 

@@ -8,26 +8,22 @@
 
 namespace pcms {
 
-// Writes a source's FP64 record (padded_dim(dim) doubles) and FP32 record
-// (padded_dim32(dim) floats, fl32(x_k - lo_k)) from its dim coordinates,
-// padding with zeros, with 16-byte stores.
+// Writes a source's FP64 record (padded_dim(dim) doubles, the padding zero,
+// with 16-byte stores) and FP32 record (dim floats, fl32(x_k - lo_k)) from its
+// dim coordinates.
 __device__ __forceinline__ void write_records(const double *__restrict__ x, int dim,
                                               const double *__restrict__ lo,
                                               double *__restrict__ r64, float *__restrict__ r32)
 {
     double v[8];
-    float w[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        v[k] = k < dim ? x[k] : 0.0;
-        w[k] = k < dim ? (float)(v[k] - lo[k]) : 0.0f;
-    }
+    for (int k = 0; k < 8; ++k) v[k] = k < dim ? x[k] : 0.0;
 #pragma unroll
     for (int k = 0; k < 6; k += 2)
         if (k < dim) *reinterpret_cast<double2 *>(r64 + k) = make_double2(v[k], v[k + 1]);
 #pragma unroll
-    for (int k = 0; k < 8; k += 4)
-        if (k < dim) *reinterpret_cast<float4 *>(r32 + k) = make_float4(w[k], w[k + 1], w[k + 2], w[k + 3]);
+    for (int k = 0; k < 5; ++k)
+        if (k < dim) r32[k] = (float)(v[k] - lo[k]);
 }
 
 // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
