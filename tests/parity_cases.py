@@ -332,3 +332,38 @@ def case_fp32_filter(be):
     for mode, kw in ((synth.FIXED, dict(radius=0.25, k_cap=40)), (synth.KNN, dict(k=13, k_cap=40))):
         p = custom(src, src[:, 0] + 2 * src[:, 1], tgt, 1, mode, **kw)
         check_same_search(be, p, f"lattice ties {mode}")
+
+
+def case_random_caps(be, trials=40, seed=7):
+    """Seeded random small problems (uniform, lattice with duplicates,
+    clustered; 1-3 dimensions; fixed, kNN beyond the cap, growing radii;
+    caps from m to 23) whose lists are mostly capped and full of exact ties:
+    the lists against brute force, and the mixed-precision search's kept
+    sources against the FP64 search's."""
+    rng = np.random.default_rng(seed)
+    for trial in range(trials):
+        d = int(rng.integers(1, 4))
+        kind = int(rng.integers(0, 3))
+        n = int(rng.integers(50, 600))
+        if kind == 0:
+            src = rng.uniform(0, 1, (n, d))
+        elif kind == 1:
+            g1 = np.arange(int(round(n ** (1 / d))) + 1) / 8.0
+            src = np.stack(np.meshgrid(*([g1] * d), indexing="ij"), -1).reshape(-1, d)
+            src = np.concatenate([src, src[::3]])
+        else:
+            src = rng.normal(0.5, 0.05, (n, d))
+        tgt = np.concatenate([src[rng.integers(0, len(src), 20)], rng.uniform(0, 1, (20, d))])
+        mode = int(rng.integers(0, 3))
+        k_cap = int(rng.integers(max(2, d + 1), 24))
+        if mode == 0:
+            kw, m = dict(radius=float(rng.uniform(0.1, 0.4)), k_cap=k_cap), synth.FIXED
+        elif mode == 1:
+            kw, m = dict(k=int(rng.integers(k_cap + 2, k_cap + 20)), k_cap=k_cap), synth.KNN
+        else:
+            kw, m = dict(radius=float(rng.uniform(0.02, 0.1)), n_min=int(rng.integers(3, 12)),
+                         k_cap=k_cap), synth.GROW
+        p = custom(src, src[:, 0], tgt, 0, m, **kw)
+        where = f"random caps {trial} (d={d}, kind={kind}, mode={m}, {kw})"
+        check_lists(be, p, where, brute=True)
+        check_same_search(be, p, where)

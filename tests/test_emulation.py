@@ -91,3 +91,7 @@ def test_emu_operator():
 
 def test_emu_fp32_filter():
     C.case_fp32_filter(BE)
+
+
+def test_emu_random_caps():
+    C.case_random_caps(BE)

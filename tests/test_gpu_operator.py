@@ -46,6 +46,10 @@ def test_fp32_filtered_search_keeps_the_fp64_lists():
     C.case_fp32_filter(SearchBackend())
 
 
+def test_random_capped_lists_with_ties():
+    C.case_random_caps(SearchBackend())
+
+
 def test_full_c3_filtered_search_keeps_the_fp64_lists():
     """Every target of the full 3-D workload: the mixed-precision search
     (FP32 records) keeps the same sources, in the same order, as FP64."""
