@@ -30,8 +30,9 @@
  *
  * Per-target status (uint8): 0 OK; 1 UNDERDETERMINED (fewer than m kept
  * sources: the paper's error condition); 2 SINGULAR (a Cholesky pivot at or
- * below 1e-13 * max diag of the moment matrix, or, in the mixed modes, an
- * iterative-refinement correction larger than the solution); 3
+ * below 1e-13 * max diag of the moment matrix -- 4e-6 * max diag in MIXED,
+ * whose FP32-accumulated moments resolve nothing finer -- or, in
+ * MIXED_REFINE, a refinement correction that stops shrinking); 3
  * RADIUS_EXHAUSTED (growing radius ran out of doublings before reaching the
  * minimum count); bit 0x10 CAPPED (more than k_cap sources were inside the
  * radius; the k_cap nearest by (distance, source index) were kept).  Targets
@@ -98,7 +99,8 @@ typedef struct {
 /* Arithmetic of the moment assembly.
  *   FP64:         everything in FP64.
  *   MIXED:        weights and the moment matrix G = P^T W P in FP32 with FP32
- *                 accumulation; Cholesky, solve and evaluation in FP64.
+ *                 accumulation; Cholesky, solve and evaluation in FP64.  No
+ *                 refinement: the error grows with the conditioning of G.
  *   MIXED_REFINE: FP32 moment matrix and an FP32 Cholesky factor of it as
  *                 the preconditioner of FP64 iterative refinement of the
  *                 shape functional y = G^{-1} e_0, the residual e_0 - G y
@@ -187,8 +189,9 @@ typedef struct pcms_operator pcms_operator;
  * the search, the moment assembly and solve of opts.precision, and the
  * shape functions of every kept source (in FP64).  The operator is library
  * owned (pcms_operator_free) and holds, per target, at most
- * pcms_operator_width(op) <= k_cap weights and source indices; the coordinates
- * are not kept.  status [n_tgt] (may be NULL) and the return code are as for
+ * pcms_operator_width(op) <= k_cap weights and source indices (the width is
+ * k_cap, or k + 8 for a KNN radius with k + 8 < k_cap); the coordinates are
+ * not kept.  status [n_tgt] (may be NULL) and the return code are as for
  * pcms_mls_transfer; on such a status code *out is still set (failed targets
  * give NaN when applied). */
 pcms_status pcms_operator_build(const double *src, int64_t n_src, int32_t dim, const double *tgt,
@@ -205,9 +208,10 @@ pcms_status pcms_operator_apply(const pcms_operator *op, const double *src_vals,
 
 /* Copy the operator to DEVICE arrays in original target order: n_kept[i]
  * (-1 for a failed target) and, for e < n_kept[i], cols[i*stride + e] (source
- * index) and weights[i*stride + e] (N); the other entries of a row are -1
- * and 0.  cols and weights may be NULL.  Entries come in search order, not
- * sorted by source index. */
+ * index) and weights[i*stride + e] (N); every other entry of the stride-long
+ * row is written as -1 and 0.  stride >= pcms_operator_width(op), else
+ * PCMS_ERR_ARG.  cols and weights may be NULL.  Entries come in search order,
+ * not sorted by source index. */
 pcms_status pcms_operator_export(const pcms_operator *op, int32_t stride, pcms_stream_t stream,
                                  int32_t *n_kept, int32_t *cols, double *weights);
 

@@ -574,7 +574,8 @@ pcms_status pcms_operator_export(const pcms_operator *op, int32_t stride, pcms_s
 {
     if (!op) return arg_error("operator is NULL");
     const Operator &o = *reinterpret_cast<const Operator *>(op);
-    if (stride < 1) return arg_error("stride must be >= 1");
+    if (stride < 1 || stride < o.width)
+        return arg_error("stride must be >= pcms_operator_width(op) (" + std::to_string(o.width) + ")");
     if (o.n_tgt > 0 && !n_kept) return arg_error("n_kept is required");
     return operator_export(o, stride, n_kept, cols, weights, (hipStream_t)stream);
 }

@@ -92,16 +92,25 @@ PCMS_HD PCMS_INLINE constexpr int tri(int a, int b)
     return a * M - a * (a - 1) / 2 + (b - a);
 }
 
+// Singularity floors of the Cholesky pivots, relative to max diag: 1e-13 for
+// moments accumulated in FP64 (and for the FP32 factor of MIXED_REFINE, whose
+// refinement judges convergence itself); 4e-6 (64 units of FP32 rounding) for
+// FP32-accumulated moments factored without refinement, whose pivots below
+// that carry no information (an exactly singular G gets pivots of FP32
+// rounding size instead of zero).
+constexpr double kPivotFloor = 1e-13;
+constexpr double kPivotFloorF32 = 4e-6;
+
 // In-place Cholesky of the packed SPD matrix A (upper triangle rows), in T,
 // overwriting it with the factor R = L^T (A = R^T R).  Returns false when a
-// pivot is not above 1e-13 * max diag(A).
+// pivot is not above tau_rel * max diag(A).
 template <int M, typename T>
-PCMS_HD PCMS_INLINE bool cholesky(T (&A)[M * (M + 1) / 2], T (&inv_diag)[M])
+PCMS_HD PCMS_INLINE bool cholesky(T (&A)[M * (M + 1) / 2], T (&inv_diag)[M], double tau_rel)
 {
     T maxd = T(0);
 #pragma unroll
     for (int i = 0; i < M; ++i) maxd = fmax(maxd, A[tri<M>(i, i)]);
-    const T tau = T(1e-13) * maxd;
+    const T tau = T(tau_rel) * maxd;
     bool ok = maxd > T(0);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
@@ -453,7 +462,7 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
             for (int j = 0; j < MM; ++j) R[j] = (double)Gm[j];
 #pragma unroll
             for (int u = 0; u < M; ++u) R[tri<M>(u, u)] += a.lambda;
-            ok = cholesky<M, double>(R, idg);
+            ok = cholesky<M, double>(R, idg, MIXED ? kPivotFloorF32 : kPivotFloor);
             chol_solve<M, double>(R, idg, y);
         } else {
             // Iterative refinement with an FP32 factor of the FP32 moments as
@@ -470,7 +479,7 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
             TA idg[M];
 #pragma unroll
             for (int u = 0; u < M; ++u) Gm[tri<M>(u, u)] += (TA)a.lambda;
-            ok = cholesky<M, TA>(Gm, idg);
+            ok = cholesky<M, TA>(Gm, idg, kPivotFloor);
             chol_solve<M, TA>(Gm, idg, y);
             double nd_prev = 0.0;
             for (int step = 0; ok && step < kMaxRefine; ++step) {

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "internal.h"
 #include "kernels.h"
 
@@ -169,6 +171,8 @@ pcms_status launch_operator(const LaunchSpec &ls, int degree, int weight, int pr
     return PCMS_OK;
 }
 
-int operator_width(const LaunchSpec &ls) { return lane_words(ls); }
+// Slots per target of an operator: every kept list fits its LDS words and
+// holds at most k_cap entries.
+int operator_width(const LaunchSpec &ls) { return std::min(lane_words(ls), ls.k_cap); }
 
 }  // namespace pcms

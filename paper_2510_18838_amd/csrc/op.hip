@@ -107,8 +107,10 @@ __global__ void k_op_export(const int32_t *__restrict__ opn, const int32_t *__re
     const int n = opn[i];
     const int64_t ti = tperm[i];
     n_kept[ti] = n;
-    for (int e = 0; e < width && e < stride; ++e) {
-        const bool ok = e < n;
+    // n <= width <= stride (checked on the host): the whole row is written,
+    // kept entries first, then -1 / 0
+    for (int e = 0; e < stride; ++e) {
+        const bool ok = e < n && e < width;
         if (cols) cols[ti * stride + e] = ok ? perm[opc[(int64_t)e * n_tgt + i]] : -1;
         if (weights) weights[ti * stride + e] = ok ? opw[(int64_t)e * n_tgt + i] : 0.0;
     }

@@ -167,10 +167,63 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _dev(t: torch.Tensor, dtype, name):
-    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
-        raise ValueError(f"{name} must be a contiguous {dtype} CUDA/HIP tensor")
+def _is_gpu(t: torch.Tensor) -> bool:
+    return t.is_cuda
+
+
+def _dev(t: torch.Tensor, dtype, name, shape=None, device=None):
+    """Checks that t is a contiguous tensor of `dtype` on a GPU device (on
+    `device` if given) with the given shape (None entries are free).  The C
+    interface receives bare pointers, so a wrong shape here would become an
+    out-of-bounds device access; it raises ValueError instead."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if shape is not None and (t.dim() != len(shape) or
+                              any(w is not None and int(v) != int(w)
+                                  for v, w in zip(t.shape, shape))):
+        want = "(" + ", ".join("*" if w is None else str(int(w)) for w in shape) + ")"
+        raise ValueError(f"{name} must have shape {want}, got {tuple(t.shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if not _is_gpu(t):
+        raise ValueError(f"{name} must be a CUDA/HIP tensor, got one on {t.device}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the other arguments on {device}")
     return t
+
+
+def _points(t: torch.Tensor, name, dim=None, device=None):
+    """[n][dim] float64 points, 1 <= dim <= 5."""
+    _dev(t, torch.float64, name, shape=(None, dim), device=device)
+    if not 1 <= t.shape[1] <= 5:
+        raise ValueError(f"{name} must have 1 to 5 columns, got {t.shape[1]}")
+    return t
+
+
+def _fields(t: torch.Tensor, n: int, name, device=None):
+    """Field values [n_fields][n] (or [n] for one field), float64."""
+    if isinstance(t, torch.Tensor) and t.dim() == 1:
+        _dev(t, torch.float64, name, shape=(n,), device=device)
+        return t.view(1, -1)
+    _dev(t, torch.float64, name, shape=(None, n), device=device)
+    if t.shape[0] < 1:
+        raise ValueError(f"{name} must hold at least one field")
+    return t
+
+
+def _outputs(out, status, nf: int, n_tgt: int, device):
+    """Caller-supplied or new output buffers [nf][n_tgt] float64 and [n_tgt] uint8."""
+    if out is None:
+        out = torch.empty((nf, n_tgt), dtype=torch.float64, device=device)
+    else:
+        _dev(out, torch.float64, "out", shape=(nf, n_tgt), device=device)
+    if status is None:
+        status = torch.empty(n_tgt, dtype=torch.uint8, device=device)
+    else:
+        _dev(status, torch.uint8, "status", shape=(n_tgt,), device=device)
+    return out, status
 
 
 def radius(mode=RADIUS_FIXED, r=0.0, k=0, n_min=0, max_iter=40) -> Radius:
@@ -217,7 +270,7 @@ def _host_scale(inv_scale, dim):
 
 def pcms_grid_build(src: torch.Tensor, inv_scale=None, cell_width=0.0, pts_per_cell=0.0,
                     stream=None) -> Grid:
-    _dev(src, torch.float64, "src")
+    _points(src, "src")
     n, dim = src.shape
     keep, g = _host_scale(inv_scale, dim)
     h = ctypes.c_void_p()
@@ -229,7 +282,7 @@ def pcms_grid_build(src: torch.Tensor, inv_scale=None, cell_width=0.0, pts_per_c
 def pcms_neighbors(grid: Grid, tgt: torch.Tensor, rad: Radius, k_cap: int, stream=None,
                    allow_status_errors=True):
     """Returns dict(nbr [n_tgt, k_cap] int32, n_kept, n_found, r2, status, code)."""
-    _dev(tgt, torch.float64, "tgt")
+    _points(tgt, "tgt", dim=grid.dim)
     n = tgt.shape[0]
     dev = tgt.device
     nbr = torch.full((n, k_cap), -1, dtype=torch.int32, device=dev)
@@ -252,17 +305,13 @@ def pcms_mls_transfer(src: torch.Tensor, src_vals: torch.Tensor, tgt: torch.Tens
                       o: Optional[MlsOpts] = None, stream=None, out: Optional[torch.Tensor] = None,
                       status: Optional[torch.Tensor] = None, allow_status_errors=True):
     """One-shot transfer.  Returns (tgt_vals [n_fields, n_tgt], status [n_tgt], code)."""
-    _dev(src, torch.float64, "src")
-    _dev(src_vals, torch.float64, "src_vals")
-    _dev(tgt, torch.float64, "tgt")
+    _points(src, "src")
     n_src, dim = src.shape
-    vals2 = src_vals if src_vals.dim() == 2 else src_vals.view(1, -1)
+    _points(tgt, "tgt", dim=dim, device=src.device)
+    vals2 = _fields(src_vals, n_src, "src_vals", device=src.device)
     nf = vals2.shape[0]
     n_tgt = tgt.shape[0]
-    if out is None:
-        out = torch.empty((nf, n_tgt), dtype=torch.float64, device=tgt.device)
-    if status is None:
-        status = torch.empty(n_tgt, dtype=torch.uint8, device=tgt.device)
+    out, status = _outputs(out, status, nf, n_tgt, src.device)
     keep, g = _host_scale(inv_scale, dim)
     o = opts() if o is None else o
     allow = _STATUS_CODES if allow_status_errors else ()
@@ -278,15 +327,11 @@ def pcms_mls_transfer_grid(grid: Grid, src_vals: torch.Tensor, tgt: torch.Tensor
                            o: Optional[MlsOpts] = None, stream=None,
                            out: Optional[torch.Tensor] = None,
                            status: Optional[torch.Tensor] = None, allow_status_errors=True):
-    _dev(src_vals, torch.float64, "src_vals")
-    _dev(tgt, torch.float64, "tgt")
-    vals2 = src_vals if src_vals.dim() == 2 else src_vals.view(1, -1)
+    _points(tgt, "tgt", dim=grid.dim)
+    vals2 = _fields(src_vals, grid.n_src, "src_vals", device=tgt.device)
     nf = vals2.shape[0]
     n_tgt = tgt.shape[0]
-    if out is None:
-        out = torch.empty((nf, n_tgt), dtype=torch.float64, device=tgt.device)
-    if status is None:
-        status = torch.empty(n_tgt, dtype=torch.uint8, device=tgt.device)
+    out, status = _outputs(out, status, nf, n_tgt, tgt.device)
     o = opts() if o is None else o
     allow = _STATUS_CODES if allow_status_errors else ()
     code = _check(lib().pcms_mls_transfer_grid(grid.handle, _ptr(vals2), nf, _ptr(tgt), n_tgt,
@@ -317,16 +362,12 @@ class BatchProblem:
 
     def __init__(self, src, src_vals, tgt, basis_degree, rad: Radius, k_cap, inv_scale=None,
                  out=None, status=None):
-        _dev(src, torch.float64, "src")
-        _dev(tgt, torch.float64, "tgt")
+        _points(src, "src")
+        _points(tgt, "tgt", dim=src.shape[1], device=src.device)
         self.src, self.tgt = src, tgt
-        self.src_vals = _dev(src_vals if src_vals.dim() == 2 else src_vals.view(1, -1),
-                             torch.float64, "src_vals")
+        self.src_vals = _fields(src_vals, src.shape[0], "src_vals", device=src.device)
         nf, n_tgt = self.src_vals.shape[0], tgt.shape[0]
-        self.out = out if out is not None else torch.empty((nf, n_tgt), dtype=torch.float64,
-                                                           device=tgt.device)
-        self.status = status if status is not None else torch.empty(n_tgt, dtype=torch.uint8,
-                                                                    device=tgt.device)
+        self.out, self.status = _outputs(out, status, nf, n_tgt, src.device)
         self.basis_degree, self.rad, self.k_cap = int(basis_degree), rad, int(k_cap)
         self.inv_scale = inv_scale
 
@@ -407,12 +448,16 @@ class Operator:
     def __init__(self, src: torch.Tensor, tgt: torch.Tensor, basis_degree: int, rad: Radius,
                  k_cap: int, inv_scale=None, o: Optional[MlsOpts] = None, stream=None,
                  status: Optional[torch.Tensor] = None, allow_status_errors=True):
-        _dev(src, torch.float64, "src")
-        _dev(tgt, torch.float64, "tgt")
+        _points(src, "src")
         n_src, dim = src.shape
+        _points(tgt, "tgt", dim=dim, device=src.device)
         self.n_src, self.n_tgt, self.k_cap = n_src, tgt.shape[0], int(k_cap)
-        self.status = status if status is not None else torch.empty(self.n_tgt, dtype=torch.uint8,
-                                                                    device=tgt.device)
+        self.device = src.device
+        if status is None:
+            status = torch.empty(self.n_tgt, dtype=torch.uint8, device=src.device)
+        else:
+            _dev(status, torch.uint8, "status", shape=(self.n_tgt,), device=src.device)
+        self.status = status
         keep, g = _host_scale(inv_scale, dim)
         o = opts() if o is None else o
         h = ctypes.c_void_p()
@@ -426,11 +471,12 @@ class Operator:
         self.width = lib().pcms_operator_width(h)
 
     def apply(self, src_vals: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
-        _dev(src_vals, torch.float64, "src_vals")
-        vals2 = src_vals if src_vals.dim() == 2 else src_vals.view(1, -1)
+        vals2 = _fields(src_vals, self.n_src, "src_vals", device=self.device)
         nf = vals2.shape[0]
         if out is None:
-            out = torch.empty((nf, self.n_tgt), dtype=torch.float64, device=src_vals.device)
+            out = torch.empty((nf, self.n_tgt), dtype=torch.float64, device=self.device)
+        else:
+            _dev(out, torch.float64, "out", shape=(nf, self.n_tgt), device=self.device)
         _check(lib().pcms_operator_apply(self.handle, _ptr(vals2), nf, _stream(stream), _ptr(out)))
         return out
 

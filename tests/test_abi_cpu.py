@@ -181,3 +181,89 @@ def test_operator_argument_checks():
     assert L.pcms_operator_export(None, 8, None, FAKE, None, None) == pcms.PCMS_ERR_ARG
     assert L.pcms_operator_width(None) == 0
     assert L.pcms_operator_free(None) == pcms.PCMS_OK
+
+
+# --- the Python binding's shape checks (no GPU: a ValueError is raised before
+# any library call; the GPU-device test is relaxed so CPU tensors reach them)
+
+@pytest.fixture
+def cpu_as_gpu(monkeypatch):
+    import torch
+    monkeypatch.setattr(pcms, "_is_gpu", lambda t: True)
+    return torch
+
+
+def _f64(torch, *shape):
+    return torch.zeros(*shape, dtype=torch.float64)
+
+
+@needs_lib
+@pytest.mark.parametrize("case,msg", [
+    ("src_1d", "src must have shape"),
+    ("src_6cols", "1 to 5 columns"),
+    ("tgt_dim", "tgt must have shape"),
+    ("vals_len", "src_vals must have shape"),
+    ("vals_2d_len", "src_vals must have shape"),
+    ("vals_dtype", "src_vals must be torch.float64"),
+    ("out_shape", "out must have shape"),
+    ("out_dtype", "out must be torch.float64"),
+    ("status_len", "status must have shape"),
+    ("status_dtype", "status must be torch.uint8"),
+    ("tgt_strided", "tgt must be contiguous"),
+])
+def test_binding_rejects_bad_shapes(cpu_as_gpu, case, msg):
+    torch = cpu_as_gpu
+    src, vals, tgt = _f64(torch, 100, 2), _f64(torch, 3, 100), _f64(torch, 10, 2)
+    out, status = None, None
+    if case == "src_1d":
+        src = _f64(torch, 100)
+    elif case == "src_6cols":
+        src, tgt = _f64(torch, 100, 6), _f64(torch, 10, 6)
+    elif case == "tgt_dim":
+        tgt = _f64(torch, 10, 3)
+    elif case == "vals_len":
+        vals = _f64(torch, 99)
+    elif case == "vals_2d_len":
+        vals = _f64(torch, 3, 101)
+    elif case == "vals_dtype":
+        vals = torch.zeros(3, 100, dtype=torch.float32)
+    elif case == "out_shape":
+        out = _f64(torch, 3, 9)
+    elif case == "out_dtype":
+        out = torch.zeros(3, 10, dtype=torch.float32)
+    elif case == "status_len":
+        status = torch.zeros(11, dtype=torch.uint8)
+    elif case == "status_dtype":
+        status = torch.zeros(10, dtype=torch.int32)
+    elif case == "tgt_strided":
+        tgt = _f64(torch, 2, 10).t()
+    with pytest.raises(ValueError, match=msg):
+        pcms.pcms_mls_transfer(src, vals, tgt, 1, pcms.radius(pcms.RADIUS_FIXED, r=0.1), 32,
+                               out=out, status=status)
+
+
+@needs_lib
+def test_binding_rejects_bad_shapes_on_grid_operator_and_batch(cpu_as_gpu):
+    torch = cpu_as_gpu
+    g = pcms.Grid(None, 100, 2)           # a handle-less stand-in: checks run first
+    rad = pcms.radius(pcms.RADIUS_FIXED, r=0.1)
+    with pytest.raises(ValueError, match="tgt must have shape"):
+        pcms.pcms_neighbors(g, _f64(torch, 10, 3), rad, 16)
+    with pytest.raises(ValueError, match="src_vals must have shape"):
+        pcms.pcms_mls_transfer_grid(g, _f64(torch, 2, 50), _f64(torch, 10, 2), 1, rad, 16)
+    with pytest.raises(ValueError, match="out must have shape"):
+        pcms.pcms_mls_transfer_grid(g, _f64(torch, 2, 100), _f64(torch, 10, 2), 1, rad, 16,
+                                    out=_f64(torch, 1, 10))
+    with pytest.raises(ValueError, match="src_vals must have shape"):
+        pcms.BatchProblem(_f64(torch, 100, 3), _f64(torch, 2, 90), _f64(torch, 7, 3), 1, rad, 16)
+    with pytest.raises(ValueError, match="tgt must have shape"):
+        pcms.BatchProblem(_f64(torch, 100, 3), _f64(torch, 2, 100), _f64(torch, 7, 2), 1, rad, 16)
+    op = pcms.Operator.__new__(pcms.Operator)   # the apply-side checks of a built operator
+    op.n_src, op.n_tgt, op.device, op.handle = 100, 10, torch.device("cpu"), None
+    with pytest.raises(ValueError, match="src_vals must have shape"):
+        op.apply(_f64(torch, 4, 99))
+    with pytest.raises(ValueError, match="out must have shape"):
+        op.apply(_f64(torch, 4, 100), out=_f64(torch, 4, 11))
+    with pytest.raises(ValueError, match="status must have shape"):
+        pcms.Operator(_f64(torch, 100, 2), _f64(torch, 10, 2), 1, rad, 16,
+                      status=torch.zeros(9, dtype=torch.uint8))

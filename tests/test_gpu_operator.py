@@ -25,7 +25,13 @@ class OpBackend:
         torch.cuda.synchronize()
         r = dict(n_kept=n_kept.cpu().numpy(), cols=cols.cpu().numpy(), weights=w.cpu().numpy(),
                  status=op.status.cpu().numpy())
+        assert op.width <= prob.k_cap
         op.free()
+        # every row is written in full: kept entries, then -1 and 0
+        slot = np.arange(prob.k_cap)[None, :]
+        pad = slot >= np.maximum(r["n_kept"], 0)[:, None]
+        assert (r["cols"][pad] == -1).all() and (r["weights"][pad] == 0.0).all(), \
+            "operator export: row padding not written"
         return r
 
 
