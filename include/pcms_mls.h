@@ -41,6 +41,7 @@
 #ifndef PCMS_MLS_H
 #define PCMS_MLS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -308,6 +309,37 @@ typedef struct {
  * synchronises it. */
 pcms_status pcms_autotune(const pcms_problem *sample, int32_t n, const pcms_batch_opts *opts,
                           const char *cache_path, pcms_stream_t stream, pcms_tune_result *out);
+
+/* ---------------------------------------------------------------------- */
+/* Allocation-free transfer on a prebuilt grid.                            */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of the fixed device workspace of pcms_mls_transfer_grid_noalloc. */
+#define PCMS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, checks, results and return codes as pcms_mls_transfer_grid,
+ * but the call allocates nothing (no hipMalloc, hipMallocAsync, hipFree or
+ * event creation): its workspace -- status counts, target order, sort
+ * buffers and bucket-ordered field records, about
+ * 8 * n_src * (n_fields rounded up to even) + 28 * n_tgt bytes -- is a fixed
+ * device array of PCMS_NOALLOC_SCRATCH_BYTES per GPU, which the library holds
+ * from the moment it is loaded on that GPU until the process ends.  A call
+ * needing more returns PCMS_ERR_ARG before any HIP call.  PCMS_PROFILE is
+ * rejected (PCMS_ERR_ARG).  Every call on one GPU uses that GPU's one array:
+ * calls that overlap on the same GPU (other streams, other threads) race and
+ * give wrong results; serialise them.  The grid must be built beforehand
+ * (pcms_grid_build allocates). */
+pcms_status pcms_mls_transfer_grid_noalloc(const pcms_grid *grid, const double *src_vals,
+                                           int32_t n_fields, const double *tgt, int64_t n_tgt,
+                                           int32_t basis_degree, const pcms_radius *radius,
+                                           int32_t k_cap, const pcms_mls_opts *opts,
+                                           pcms_stream_t stream, double *tgt_vals,
+                                           uint8_t *status);
+
+/* PCMS_NOALLOC_SCRATCH_BYTES as built into the library. */
+size_t pcms_noalloc_scratch_bytes(void);
 
 /* Phase times in milliseconds of the calling thread's last call made with
  * PCMS_PROFILE, measured with HIP events on that call's stream: [0] grid

@@ -207,6 +207,8 @@ pcms_status profile_end()
 
 }  // namespace
 
+void profile_off() { g_prof.on = false; }
+
 void set_error(const std::string &msg) { g_last_error = msg; }
 
 pcms_status hip_fail(hipError_t e, const char *what)
@@ -236,6 +238,79 @@ pcms_status scratch_alloc(void **p, size_t bytes, hipStream_t s)
 void scratch_free(void *p, hipStream_t s)
 {
     if (p) (void)hipFreeAsync(p, s);
+}
+
+namespace {
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+// workspace of a transfer on a grid: [summary | tperm | svals | sort buffers]
+struct TransferWs {
+    size_t off_tperm, off_svals, off_sort, bytes;
+    TransferWs(int64_t n_src, int n_fields, int64_t n_tgt)
+    {
+        off_tperm = 256;
+        off_svals = off_tperm + align256(sizeof(int) * (size_t)n_tgt);
+        off_sort = off_svals + align256(sizeof(double) * (size_t)n_src * padded_dim(n_fields));
+        bytes = off_sort + sort_targets_bytes(n_tgt);
+    }
+};
+}  // namespace
+
+size_t transfer_ws_bytes(int64_t n_src, int n_fields, int64_t n_tgt)
+{
+    return TransferWs(n_src, n_fields, n_tgt).bytes;
+}
+
+pcms_status transfer_on_grid(const Grid *g, const double *src_vals, int32_t n_fields,
+                             const double *tgt, int64_t n_tgt, int32_t degree,
+                             const pcms_radius *radius, int32_t k_cap, const pcms_mls_opts *opts,
+                             hipStream_t s, double *tgt_vals, uint8_t *status, void *ws)
+{
+    pcms_mls_opts o;
+    pcms_mls_opts_default(&o);
+    if (opts) o = *opts;
+    const bool async = (o.flags & PCMS_ASYNC) != 0;
+    const TransferWs L(g->n_src, n_fields, n_tgt);
+    Scratch sc;
+    sc.s = s;
+    pcms_status st;
+    if (!ws) {
+        if ((st = scratch_alloc(&sc.p, L.bytes, s)) != PCMS_OK) return st;
+        ws = sc.p;
+    }
+    int32_t *summary = async ? o.summary : (int32_t *)ws;
+    int *tperm = (int *)((char *)ws + L.off_tperm);
+    double *svals = (double *)((char *)ws + L.off_svals);
+    if ((st = zero_ints(summary, 4, s)) != PCMS_OK) return st;
+    if ((st = g_prof.mark(1)) != PCMS_OK) return st;
+    if ((st = sort_targets(g, tgt, n_tgt, tperm, s, (char *)ws + L.off_sort)) != PCMS_OK) return st;
+    if ((st = g_prof.mark(2)) != PCMS_OK) return st;
+    if ((st = gather_values(g, src_vals, n_fields, svals, s)) != PCMS_OK) return st;
+    if ((st = g_prof.mark(3)) != PCMS_OK) return st;
+    LaunchSpec ls{g, tgt, tperm, n_tgt, *radius, k_cap, o.block, summary};
+    st = launch_transfer(ls, svals, n_fields, degree, o.weight, o.precision, o.lambda, tgt_vals,
+                         status, s);
+    if (st != PCMS_OK) return st;
+    if ((st = g_prof.mark(4)) != PCMS_OK) return st;
+    if ((st = profile_end()) != PCMS_OK) return st;
+    return finish(summary, async, s, true);
+}
+
+pcms_status check_transfer_args(int64_t n_src, int32_t dim, const double *src_vals,
+                                int32_t n_fields, const double *tgt, int64_t n_tgt, int32_t degree,
+                                const pcms_radius *radius, int32_t k_cap,
+                                const pcms_mls_opts *opts, double *tgt_vals)
+{
+    if (dim < 1 || dim > kMaxDim) return arg_error("dim must be in [1, 5]");
+    if (degree < 0 || degree > 2) return arg_error("basis_degree must be in [0, 2]");
+    if (n_fields < 1) return arg_error("n_fields must be >= 1");
+    if (n_tgt < 0 || n_tgt >= ((int64_t)1 << 31) / 2) return arg_error("n_tgt must be in [0, 2^30)");
+    const int m = num_monomials(dim, degree);
+    if (k_cap < m || k_cap > kMaxKcap) return arg_error("k_cap must be in [m, 256]");
+    pcms_status st = check_radius(radius, n_src);
+    if (st != PCMS_OK) return st;
+    if ((st = check_opts(opts)) != PCMS_OK) return st;
+    if (n_tgt > 0 && (!src_vals || !tgt || !tgt_vals)) return arg_error("src_vals, tgt and tgt_vals are required");
+    return PCMS_OK;
 }
 
 }  // namespace pcms
@@ -350,59 +425,6 @@ pcms_status pcms_neighbors(const pcms_grid *grid, const double *tgt, int64_t n_t
     return finish(summary, false, s, false);
 }
 
-static pcms_status transfer_common(const Grid *g, const double *src_vals, int32_t n_fields,
-                                   const double *tgt, int64_t n_tgt, int32_t degree,
-                                   const pcms_radius *radius, int32_t k_cap,
-                                   const pcms_mls_opts *opts, hipStream_t s, double *tgt_vals,
-                                   uint8_t *status)
-{
-    pcms_mls_opts o;
-    pcms_mls_opts_default(&o);
-    if (opts) o = *opts;
-    const bool async = (o.flags & PCMS_ASYNC) != 0;
-    Scratch sc;
-    sc.s = s;
-    size_t off_tperm = 64;
-    size_t off_svals = off_tperm + ((sizeof(int) * (size_t)n_tgt + 255) & ~(size_t)255);
-    size_t bytes = off_svals + sizeof(double) * (size_t)g->n_src * padded_dim(n_fields);
-    pcms_status st = scratch_alloc(&sc.p, bytes, s);
-    if (st != PCMS_OK) return st;
-    int32_t *summary = async ? o.summary : (int32_t *)sc.p;
-    int *tperm = (int *)((char *)sc.p + off_tperm);
-    double *svals = (double *)((char *)sc.p + off_svals);
-    if ((st = zero_ints(summary, 4, s)) != PCMS_OK) return st;
-    if ((st = g_prof.mark(1)) != PCMS_OK) return st;
-    if ((st = sort_targets(g, tgt, n_tgt, tperm, s)) != PCMS_OK) return st;
-    if ((st = g_prof.mark(2)) != PCMS_OK) return st;
-    if ((st = gather_values(g, src_vals, n_fields, svals, s)) != PCMS_OK) return st;
-    if ((st = g_prof.mark(3)) != PCMS_OK) return st;
-    LaunchSpec ls{g, tgt, tperm, n_tgt, *radius, k_cap, o.block, summary};
-    st = launch_transfer(ls, svals, n_fields, degree, o.weight, o.precision, o.lambda, tgt_vals,
-                         status, s);
-    if (st != PCMS_OK) return st;
-    if ((st = g_prof.mark(4)) != PCMS_OK) return st;
-    if ((st = profile_end()) != PCMS_OK) return st;
-    return finish(summary, async, s, true);
-}
-
-static pcms_status check_transfer_args(int64_t n_src, int32_t dim, const double *src_vals,
-                                       int32_t n_fields, const double *tgt, int64_t n_tgt,
-                                       int32_t degree, const pcms_radius *radius, int32_t k_cap,
-                                       const pcms_mls_opts *opts, double *tgt_vals)
-{
-    if (dim < 1 || dim > kMaxDim) return arg_error("dim must be in [1, 5]");
-    if (degree < 0 || degree > 2) return arg_error("basis_degree must be in [0, 2]");
-    if (n_fields < 1) return arg_error("n_fields must be >= 1");
-    if (n_tgt < 0 || n_tgt >= ((int64_t)1 << 31) / 2) return arg_error("n_tgt must be in [0, 2^30)");
-    const int m = num_monomials(dim, degree);
-    if (k_cap < m || k_cap > kMaxKcap) return arg_error("k_cap must be in [m, 256]");
-    pcms_status st = check_radius(radius, n_src);
-    if (st != PCMS_OK) return st;
-    if ((st = check_opts(opts)) != PCMS_OK) return st;
-    if (n_tgt > 0 && (!src_vals || !tgt || !tgt_vals)) return arg_error("src_vals, tgt and tgt_vals are required");
-    return PCMS_OK;
-}
-
 pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, const double *src_vals,
                               int32_t n_fields, const double *tgt, int64_t n_tgt,
                               int32_t basis_degree, const pcms_radius *radius, int32_t k_cap,
@@ -443,8 +465,8 @@ pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, con
     g.spts = (double *)((char *)sc.p + o_spts);
     g.spts32 = (float *)((char *)sc.p + o_s32);
     if ((st = build_grid_device(&g, src, cw, ppc, s)) != PCMS_OK) return st;
-    return transfer_common(&g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts, s,
-                           tgt_vals, status);
+    return transfer_on_grid(&g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts,
+                            s, tgt_vals, status, nullptr);
 }
 
 pcms_status pcms_mls_transfer_grid(const pcms_grid *grid, const double *src_vals, int32_t n_fields,
@@ -461,8 +483,8 @@ pcms_status pcms_mls_transfer_grid(const pcms_grid *grid, const double *src_vals
     if (n_tgt == 0) return PCMS_OK;
     if ((st = profile_begin(opts, (hipStream_t)stream)) != PCMS_OK) return st;
     if ((st = g_prof.mark(1)) != PCMS_OK) return st;   // no grid build in this call
-    return transfer_common(g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts,
-                           (hipStream_t)stream, tgt_vals, status);
+    return transfer_on_grid(g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts,
+                            (hipStream_t)stream, tgt_vals, status, nullptr);
 }
 
 pcms_status pcms_operator_build(const double *src, int64_t n_src, int32_t dim, const double *tgt,

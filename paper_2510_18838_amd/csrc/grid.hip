@@ -445,15 +445,19 @@ pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
     return PCMS_OK;
 }
 
+size_t sort_targets_bytes(int64_t n_tgt) { return sort_scratch_bytes((int)n_tgt); }
+
 pcms_status sort_targets(const Grid *grid, const double *tgt, int64_t n_tgt, int *tperm,
-                         hipStream_t s)
+                         hipStream_t s, void *ws)
 {
     const int n = (int)n_tgt;
-    size_t bytes = sort_scratch_bytes(n);
     void *raw = nullptr;
-    pcms_status st = scratch_alloc(&raw, bytes, s);
-    if (st != PCMS_OK) return st;
-    char *cur = (char *)raw;
+    pcms_status st;
+    if (!ws) {
+        st = scratch_alloc(&raw, sort_scratch_bytes(n), s);
+        if (st != PCMS_OK) return st;
+    }
+    char *cur = (char *)(ws ? ws : raw);
     unsigned *k0 = (unsigned *)cur;
     cur += sizeof(unsigned) * (size_t)n;
     unsigned *k1 = (unsigned *)cur;
@@ -486,7 +490,7 @@ pcms_status sort_targets(const Grid *grid, const double *tgt, int64_t n_tgt, int
     }
     st = radix_sort(k0, tperm, k1, v1, n, bits, hist, scan_scratch, s);
     if (st != PCMS_OK) return st;
-    scratch_free(raw, s);
+    if (raw) scratch_free(raw, s);
     return PCMS_OK;
 }
 

@@ -47,9 +47,12 @@ int cells_cap_for(int64_t n_src);
 // cell_width > 0: metric bucket width; else buckets sized for pts_per_cell.
 pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
                               double pts_per_cell, hipStream_t s);
-// Target ordering: tperm[i] = index of the target at sorted position i.
+// Target ordering: tperm[i] = index of the target at sorted position i.  Its
+// sort buffers are `ws` (sort_targets_bytes(n_tgt) bytes, 256-byte aligned)
+// when given, else stream-ordered scratch.
+size_t sort_targets_bytes(int64_t n_tgt);
 pcms_status sort_targets(const Grid *grid, const double *tgt, int64_t n_tgt, int *tperm,
-                         hipStream_t s);
+                         hipStream_t s, void *ws = nullptr);
 // Sorted field copy: svals[p * n_fields + l] = vals[l * n_src + perm[p]].
 pcms_status gather_values(const Grid *grid, const double *vals, int n_fields, double *svals,
                           hipStream_t s);
@@ -63,6 +66,26 @@ size_t sort_hist_ints(int n);
 size_t sort_scan_ints(int n);
 // Smallest b <= 32 with 2^b >= bound.
 int bits_for(double bound);
+
+// transfer on a built grid (abi.hip) -------------------------------------------
+// Bytes of the workspace of transfer_on_grid: status counts, target order,
+// its sort buffers and the bucket-ordered field records.
+size_t transfer_ws_bytes(int64_t n_src, int n_fields, int64_t n_tgt);
+// Target ordering, field gather, search-and-fit and the status plumbing of
+// a transfer on grid g (arguments already validated).  ws: a device
+// workspace of transfer_ws_bytes(...) bytes, 256-byte aligned, or NULL for
+// stream-ordered scratch.
+pcms_status transfer_on_grid(const Grid *g, const double *src_vals, int32_t n_fields,
+                             const double *tgt, int64_t n_tgt, int32_t degree,
+                             const pcms_radius *radius, int32_t k_cap, const pcms_mls_opts *opts,
+                             hipStream_t s, double *tgt_vals, uint8_t *status, void *ws);
+// Turns off the calling thread's phase timing for the next transfer.
+void profile_off();
+// Host-side validation of a transfer's arguments (PCMS_ERR_ARG with a message).
+pcms_status check_transfer_args(int64_t n_src, int32_t dim, const double *src_vals,
+                                int32_t n_fields, const double *tgt, int64_t n_tgt, int32_t degree,
+                                const pcms_radius *radius, int32_t k_cap,
+                                const pcms_mls_opts *opts, double *tgt_vals);
 
 // search and fit (mls.hip) ----------------------------------------------------
 struct LaunchSpec {

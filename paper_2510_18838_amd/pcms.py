@@ -37,7 +37,8 @@ EXPORTED = ("pcms_mls_opts_default", "pcms_grid_build", "pcms_grid_free", "pcms_
             "pcms_last_error", "pcms_batch_opts_default", "pcms_batch_plan_create",
             "pcms_batch_plan_exec", "pcms_batch_plan_free", "pcms_autotune",
             "pcms_operator_build", "pcms_operator_apply", "pcms_operator_export",
-            "pcms_operator_width", "pcms_operator_free")
+            "pcms_operator_width", "pcms_operator_free", "pcms_mls_transfer_grid_noalloc",
+            "pcms_noalloc_scratch_bytes")
 
 
 class PcmsError(RuntimeError):
@@ -104,6 +105,10 @@ def lib() -> ctypes.CDLL:
     L.pcms_mls_transfer_grid.argtypes = [P, P, i32, P, i64, i32, ctypes.POINTER(Radius), i32,
                                          ctypes.POINTER(MlsOpts), P, P, P]
     L.pcms_mls_transfer_grid.restype = i32
+    L.pcms_mls_transfer_grid_noalloc.argtypes = L.pcms_mls_transfer_grid.argtypes
+    L.pcms_mls_transfer_grid_noalloc.restype = i32
+    L.pcms_noalloc_scratch_bytes.argtypes = []
+    L.pcms_noalloc_scratch_bytes.restype = ctypes.c_size_t
     L.pcms_last_phase_ms.argtypes = [P, i32]
     L.pcms_last_phase_ms.restype = i32
     L.pcms_version.argtypes = []
@@ -339,6 +344,34 @@ def pcms_mls_transfer_grid(grid: Grid, src_vals: torch.Tensor, tgt: torch.Tensor
                                                ctypes.byref(o), _stream(stream), _ptr(out),
                                                _ptr(status)), allow)
     return out, status, code
+
+
+def pcms_mls_transfer_grid_noalloc(grid: Grid, src_vals: torch.Tensor, tgt: torch.Tensor,
+                                   basis_degree: int, rad: Radius, k_cap: int,
+                                   out: torch.Tensor, status: torch.Tensor,
+                                   o: Optional[MlsOpts] = None, stream=None,
+                                   allow_status_errors=True):
+    """The allocation-free transfer on a prebuilt grid: the caller passes the
+    output buffers, and the library's work space is its fixed device array.
+    Returns (tgt_vals, status, code)."""
+    _points(tgt, "tgt", dim=grid.dim)
+    vals2 = _fields(src_vals, grid.n_src, "src_vals", device=tgt.device)
+    nf = vals2.shape[0]
+    n_tgt = tgt.shape[0]
+    _dev(out, torch.float64, "out", shape=(nf, n_tgt), device=tgt.device)
+    _dev(status, torch.uint8, "status", shape=(n_tgt,), device=tgt.device)
+    o = opts() if o is None else o
+    allow = _STATUS_CODES if allow_status_errors else ()
+    code = _check(lib().pcms_mls_transfer_grid_noalloc(grid.handle, _ptr(vals2), nf, _ptr(tgt),
+                                                       n_tgt, int(basis_degree), ctypes.byref(rad),
+                                                       int(k_cap), ctypes.byref(o),
+                                                       _stream(stream), _ptr(out), _ptr(status)),
+                  allow)
+    return out, status, code
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().pcms_noalloc_scratch_bytes())
 
 
 def radius_of(prob) -> Radius:
