@@ -45,14 +45,94 @@ METRIC = "target pts/sec, 3D quadratic MLS transfer: mixed vs FP64 at ≤1e-6 re
 # VALU peak: 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.  FP32 and
 # FP64 vector FMA issue at the same rate; packed FP32 is not used.
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# Algorithmic flops per target of the search-and-fit kernel (3-D quadratic,
-# kNN-40 radius, 39 weighted neighbours), see the design notes:
-#   moment assembly  39 x (10 weighted monomials + 55 FMAs of G) = 39 x 120
-#   shape functions  39 x (10 FMAs p.y + 1 + 8 field FMAs)        = 39 x 38
-#   solve            Cholesky m^3/3 + two triangular solves 2 m^2 ~ 530
-#   search           exact FP64 distance (3 sub, 3 FMA) for the 6.4 x 39
-#                    candidates of a one-radius bucket stencil     = 250 x 9
-ALG_FLOPS_PER_TARGET = 39 * 120 + 39 * 38 + 530 + 250 * 9
+HBM_PEAK_GBS = 8000.0
+# Algorithmic cost per target of the search-and-fit kernel, per workload (the
+# survey's cost model): flops = distinct-moment assembly + single-right-hand-
+# side solve + exact FP64 distance tests of a one-radius bucket stencil; HBM
+# bytes of a fused search-and-fit (no materialised lists) = 40 d + 12 +
+# 24 n_f (sorted coordinates and FP32 records, targets, field records,
+# outputs).
+COST = {
+    "c1": {"flops": 1200 + 27 + 400, "bytes": 40 * 2 + 12 + 24 * 1},
+    "c2": {"flops": 4000 + 144 + 700, "bytes": 40 * 2 + 12 + 24 * 4},
+    "c3": {"flops": 8100 + 530 + 2300, "bytes": 40 * 3 + 12 + 24 * 8},
+    "c5": {"flops": 9700 + 144 + 44000, "bytes": 40 * 5 + 12 + 24 * 4},
+}
+
+
+def batch_alg_bytes(probs):
+    """Fused-kernel bytes of the batched workload: the per-target figure
+    40 d + 12 + 24 n_f split evenly between a problem's sources and targets
+    (the two are equal in number in the other workloads)."""
+    return sum((p.src.shape[0] + p.tgt.shape[0]) * (20 * p.dim + 6 + 12 * p.n_fields)
+               for p in probs)
+
+
+def roofline(name, n_tgt, kernel_ms, traffic=None, kernel="k_transfer"):
+    """Both bounds of a search-and-fit launch: the VALU one (the binding one
+    for these kernels) and the HBM one, from the algorithmic cost per target
+    and the kernel's event-timed duration."""
+    c = COST[name]
+    tf = c["flops"] * n_tgt / (kernel_ms * 1e-3) / 1e12
+    gbs = c["bytes"] * n_tgt / (kernel_ms * 1e-3) / 1e9
+    r = {"bound": "alu", "kernel": kernel, "achieved": tf, "peak": VALU_PEAK_TFLOPS,
+         "unit": "TFLOP/s", "frac": tf / VALU_PEAK_TFLOPS, "traffic": traffic,
+         "alg_flops_per_target": c["flops"], "units_per_launch": int(n_tgt),
+         "kernel_ms": kernel_ms,
+         "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": gbs / HBM_PEAK_GBS, "alg_bytes_per_target": c["bytes"]}}
+    if traffic:
+        r["hbm"]["counted_gbs"] = traffic / (kernel_ms * 1e-3) / 1e9
+        r["hbm"]["counted_frac"] = r["hbm"]["counted_gbs"] / HBM_PEAK_GBS
+    return r
+
+
+def time_transfer(torch, pcms, p, src, vals, tgt, rad, precision, steps, warmup, out, st,
+                  summary):
+    """K one-shot transfers enqueued back to back (PCMS_ASYNC, statuses into a
+    device summary), bracketed by device synchronisations: ms per step from
+    the host clock over the K steps, each step's duration from HIP events
+    recorded on the launch stream (median, min), and the phases' HIP-event
+    times inside the library (PCMS_PROFILE, averaged over the K steps)."""
+    o = pcms.opts(precision=precision, flags=pcms.PROFILE | pcms.ASYNC, summary=summary)
+
+    def call():
+        pcms.pcms_mls_transfer(src, vals, tgt, p.degree, rad, p.k_cap, inv_scale=p.inv_scale,
+                               o=o, out=out, status=st)
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    pcms.phase_ms_sum(reset=True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record()
+        call()
+        e1.record()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    per = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    calls, sums = pcms.phase_ms_sum(reset=True)
+    phases = {k: v / max(calls, 1) for k, v in sums.items()}
+    return {"ms_per_step": ms, "ms_median": float(np.median(per)), "ms_min": float(per[0]),
+            "phases_ms": phases}
+
+
+def oracle_error(orc, p, out, st, n_sample, seed):
+    """Max over fields of the inf-norm error against the oracle over the
+    valid targets of a seeded sample (the accuracy gate's measure)."""
+    rng = np.random.default_rng(seed)
+    m = p.tgt.shape[0]
+    idx = np.sort(rng.choice(m, size=min(n_sample, m), replace=False))
+    ref = orc.transfer(p.src, p.vals, p.tgt[idx], p.degree, **orc.problem_kwargs(p))
+    got = out[:, idx]
+    ok = ((ref["status"] & 0xF) == 0) & (st[idx] == ref["status"])
+    if not ok.any():
+        return None, 0
+    err = max(float(np.abs(got[l, ok] - ref["out"][l, ok]).max() /
+                    np.abs(ref["out"][l, ok]).max()) for l in range(p.n_fields))
+    return err, int(ok.sum())
 
 
 def log(msg):
@@ -68,10 +148,11 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_digest):
-    """HBM traffic per launch from the committed counter summary, if it was
-    taken on the current kernel sources."""
-    p = os.path.join(ROOT, "profiles", "traffic_c3.json")
+def load_traffic(name, kernel_digest):
+    """HBM bytes per launch of the workload's search-and-fit kernel from the
+    committed counter summary (FETCH_SIZE + WRITE_SIZE, calibrated), if it
+    was taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     if not os.path.exists(p):
         return None
     with open(p) as fh:
@@ -122,6 +203,9 @@ def operator_leg(torch, pcms, p, src, tgt, vals, rad, steps, dev):
     }
 
 
+ROUNDTRIP_LAMBDAS = (1e-8, 1e-6, 1e-4, 1e-2, 1.0)
+
+
 def roundtrip(torch, pcms, synth, dev, iters=(1, 2, 5, 10, 20, 50, 100)):
     """The paper's round-trip accuracy protocol on point clouds: the field of
     Eq. 4 on ~307k jittered-lattice points (the vertex count of the paper's
@@ -129,42 +213,63 @@ def roundtrip(torch, pcms, synth, dev, iters=(1, 2, 5, 10, 20, 50, 100)):
     with the C4 weight, linear and quadratic bases and three cut-off radii
     (in units of the source spacing h); the accuracy error of Eq. 2 (L2
     norm over the source points) after each iteration.  Both transfer
-    operators are built once and applied per iteration."""
+    operators are built once and applied per iteration.  A sweep of the
+    Tikhonov parameter of Eq. 1 (lambda, in the radius-scaled basis) follows
+    for the quadratic fits at 2.5h and 3.5h and the linear fit at 3.5h."""
     src, tgt, f = synth.roundtrip_clouds()
     h = 4.0 / 554
     s_d, t_d = torch.from_numpy(src).to(dev), torch.from_numpy(tgt).to(dev)
     fd = torch.from_numpy(f[None, :]).to(dev)
     rows = []
-    for degree in (1, 2):
-        for rr in (2.5, 3.5, 5.0):
-            rad = pcms.radius(pcms.RADIUS_FIXED, r=rr * h)
-            o = pcms.opts(precision=pcms.FP64, weight=pcms.WEIGHT_C4)
-            t0 = time.perf_counter()
-            fwd = pcms.Operator(s_d, t_d, degree, rad, 128, o=o)
-            back = pcms.Operator(t_d, s_d, degree, rad, 128, o=o)
-            torch.cuda.synchronize()
-            build = (time.perf_counter() - t0) * 1e3
-            g = fd
-            ok = torch.isfinite(back.apply(fwd.apply(g)))[0]
-            err, t0 = {}, time.perf_counter()
-            for it in range(1, max(iters) + 1):
-                g = back.apply(fwd.apply(g))
-                if it in iters:
-                    d = (g[0] - fd[0])[ok]
-                    err[it] = float(torch.linalg.norm(d) / torch.linalg.norm(fd[0][ok]))
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3 / max(iters)
-            log(f"round trip degree {degree} r={rr}h: " +
-                " ".join(f"{k}:{v:.2e}" for k, v in err.items()))
-            rows.append({"degree": degree, "radius_h": rr, "accuracy_error": err,
-                         "build_ms": build, "ms_per_iteration": ms})
-            fwd.free()
-            back.free()
+    cases = [(d, rr, 0.0) for d in (1, 2) for rr in (2.5, 3.5, 5.0)]
+    cases += [(d, rr, lam) for d, rr in ((2, 2.5), (2, 3.5), (1, 3.5)) for lam in ROUNDTRIP_LAMBDAS]
+    for degree, rr, lam in cases:
+        rad = pcms.radius(pcms.RADIUS_FIXED, r=rr * h)
+        o = pcms.opts(precision=pcms.FP64, weight=pcms.WEIGHT_C4, lam=lam)
+        t0 = time.perf_counter()
+        fwd = pcms.Operator(s_d, t_d, degree, rad, 128, o=o)
+        back = pcms.Operator(t_d, s_d, degree, rad, 128, o=o)
+        torch.cuda.synchronize()
+        build = (time.perf_counter() - t0) * 1e3
+        g = fd
+        ok = torch.isfinite(back.apply(fwd.apply(g)))[0]
+        err, t0 = {}, time.perf_counter()
+        for it in range(1, max(iters) + 1):
+            g = back.apply(fwd.apply(g))
+            if it in iters:
+                d = (g[0] - fd[0])[ok]
+                err[it] = float(torch.linalg.norm(d) / torch.linalg.norm(fd[0][ok]))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / max(iters)
+        log(f"round trip degree {degree} r={rr}h lambda={lam:g}: " +
+            " ".join(f"{k}:{v:.2e}" for k, v in err.items()))
+        rows.append({"degree": degree, "radius_h": rr, "lambda": lam, "accuracy_error": err,
+                     "build_ms": build, "ms_per_iteration": ms})
+        fwd.free()
+        back.free()
     return {"experiment": "round trip, Eq. 4 field, 2-D point clouds", "n_src": int(src.shape[0]),
             "n_tgt": int(tgt.shape[0]), "weight": "C4", "rows": rows}
 
 
-def batched_leg(torch, pcms, synth, dev, steps):
+def timed_graph(torch, plan, stream, steps, summary):
+    """Replays of a captured plan: per-replay HIP-event durations on the
+    launch stream (median, min) and the mean over the K replays."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    with torch.cuda.stream(stream):
+        for _ in range(2):          # capture, then one replay
+            plan.exec(stream=stream, summary=summary)
+        stream.synchronize()
+        for e0, e1 in ev:
+            e0.record(stream)
+            plan.exec(stream=stream, summary=summary)
+            e1.record(stream)
+        stream.synchronize()
+    per = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    return float(np.mean(per)), float(np.median(per)), float(per[0])
+
+
+def batched_leg(torch, pcms, synth, dev, steps, orc=None):
     """512 transfer problems of uneven size (1k-200k points, log-uniform),
     2-D/3-D, linear/quadratic, 1-16 fields, growing radius: the batched plan
     (MIXED_REFINE, one persistent launch replayed from a HIP graph, knobs
@@ -188,33 +293,14 @@ def batched_leg(torch, pcms, synth, dev, steps):
             f"cell factor {tune.cell_factor}")
         plan = pcms.BatchPlan(bps, pcms.batch_opts(precision=pcms.MIXED_REFINE, tune_cache=cache))
     summary = torch.zeros(4, dtype=torch.int32, device=dev)
-    with torch.cuda.stream(stream):
-        for _ in range(2):          # capture, then one replay
-            plan.exec(stream=stream, summary=summary)
-        stream.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(steps):
-            plan.exec(stream=stream, summary=summary)
-        e1.record(stream)
-        e1.synchronize()
-    ms_b = e0.elapsed_time(e1) / steps
-    log(f"batched MIXED_REFINE: {ms_b:.3f} ms per batch")
+    ms_b, med_b, min_b = timed_graph(torch, plan, stream, steps, summary)
+    log(f"batched MIXED_REFINE: {ms_b:.3f} ms per batch (median {med_b:.3f}, min {min_b:.3f})")
     outs_b = [bp.out.clone() for bp in bps]
     st_b = [bp.status.clone() for bp in bps]
     # the same batch in FP64 (same knobs), for the precision comparison
     plan64 = pcms.BatchPlan(bps, pcms.batch_opts(precision=pcms.FP64, block=int(tune.block),
                                                  cell_factor=float(tune.cell_factor)))
-    with torch.cuda.stream(stream):
-        for _ in range(2):
-            plan64.exec(stream=stream, summary=summary)
-        stream.synchronize()
-        e0.record(stream)
-        for _ in range(steps):
-            plan64.exec(stream=stream, summary=summary)
-        e1.record(stream)
-        e1.synchronize()
-    ms_b64 = e0.elapsed_time(e1) / steps
+    ms_b64, med_b64, min_b64 = timed_graph(torch, plan64, stream, steps, summary)
     plan64.free()
     log(f"batched FP64: {ms_b64:.3f} ms per batch")
     # the same problems through the one-problem FP64 path
@@ -240,13 +326,32 @@ def batched_leg(torch, pcms, synth, dev, steps):
         err = max(err, float(((outs_b[q][:, ok] - ref).abs().amax(dim=1) /
                               ref.abs().amax(dim=1).clamp_min(1e-300)).max()))
     plan.free()
+    oerr = None
+    if orc is not None:
+        # MIXED_REFINE against the oracle on 300 targets of each of 16 problems
+        rng = np.random.default_rng(44)
+        oerr = 0.0
+        for q in sorted(rng.choice(len(probs), size=16, replace=False)):
+            e, _ = oracle_error(orc, probs[q], outs_b[q].cpu().numpy(), st_b[q].cpu().numpy(),
+                                n_sample=300, seed=int(q))
+            if e is not None:
+                oerr = max(oerr, e)
+    alg = batch_alg_bytes(probs)
+    gbs = alg / (med_b * 1e-3) / 1e9
     return {
         "workload": "512 problems: n_src, n_tgt log-uniform in [1e3, 2e5], d in {2, 3}, degree "
                     "in {1, 2}, 1-16 fields, growing radius, k_cap 32-64",
         "n_problems": len(bps), "n_tgt": int(n_tgt),
-        "mixed_refine_batched": {"ms": ms_b, "value": n_tgt / (ms_b / 1e3), "unit": "target pts/s",
-                                 "launch": "one persistent kernel, HIP graph replay"},
-        "fp64_batched": {"ms": ms_b64, "value": n_tgt / (ms_b64 / 1e3), "unit": "target pts/s",
+        "mixed_refine_batched": {"ms": ms_b, "ms_median": med_b, "ms_min": min_b,
+                                 "value": n_tgt / (ms_b / 1e3), "unit": "target pts/s",
+                                 "launch": "one persistent kernel, HIP graph replay",
+                                 "max_rel_err_vs_oracle_sample": oerr},
+        "roofline": {"bound": "hbm", "kernel": "one graph launch (grid builds, target order, "
+                     "field records, persistent k_batch_transfer)", "achieved": gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": None, "alg_bytes_per_launch": alg, "launch_ms_median": med_b},
+        "fp64_batched": {"ms": ms_b64, "ms_median": med_b64, "ms_min": min_b64,
+                         "value": n_tgt / (ms_b64 / 1e3), "unit": "target pts/s",
                          "launch": "the same plan in FP64"},
         "fp64_unbatched": {"ms": ms_u, "value": n_tgt / (ms_u / 1e3), "unit": "target pts/s",
                            "launch": "one one-shot call per problem"},
@@ -257,14 +362,17 @@ def batched_leg(torch, pcms, synth, dev, steps):
     }
 
 
-def configs_leg(torch, pcms, synth, dev, steps):
+def configs_leg(torch, pcms, synth, dev, steps, orc=None):
     """The other single-GPU workloads: the 2-D lattice transfer (1M -> 1M,
     quadratic, fixed radius 3.5 cells, 4 fields), the 5-D transfer (2M -> 2M,
     linear, growing radius in a standardising metric, 4 fields) and the small
     2-D correctness case (2k -> 1.5k, linear, fixed radius): one-shot steps in
-    FP64 and MIXED_REFINE, target points per second and the mixed path's
-    error against FP64 (all targets)."""
+    FP64 and MIXED_REFINE timed like the headline, each precision's roofline
+    from its search-and-fit kernel's event time, the mixed path's error
+    against FP64 (all targets) and both against the oracle on a sample."""
     rows = {}
+    digest = source_digest()
+    summary = torch.zeros(4, dtype=torch.int32, device=dev)
     for name, make in (("c1", synth.c1), ("c2", synth.c2), ("c5", synth.c5)):
         p = make()
         src, vals, tgt = (torch.from_numpy(x).to(dev) for x in (p.src, p.vals, p.tgt))
@@ -276,33 +384,31 @@ def configs_leg(torch, pcms, synth, dev, steps):
         for label, prec in (("fp64", pcms.FP64), ("mixed_refine", pcms.MIXED_REFINE)):
             out = torch.empty((p.n_fields, m), dtype=torch.float64, device=dev)
             st = torch.empty(m, dtype=torch.uint8, device=dev)
-            o = pcms.opts(precision=prec, flags=pcms.PROFILE)
-            for _ in range(2):
-                pcms.pcms_mls_transfer(src, vals, tgt, p.degree, rad, p.k_cap,
-                                       inv_scale=p.inv_scale, o=o, out=out, status=st)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            kern = []
-            for _ in range(steps):
-                pcms.pcms_mls_transfer(src, vals, tgt, p.degree, rad, p.k_cap,
-                                       inv_scale=p.inv_scale, o=o, out=out, status=st)
-                kern.append(pcms.last_phase_ms()["search_fit"])
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3 / steps
-            row[label] = {"ms_per_step": ms, "value": m / (ms * 1e-3),
-                          "search_fit_ms": float(np.mean(kern))}
-            outs[label] = (out, st)
+            t = time_transfer(torch, pcms, p, src, vals, tgt, rad, prec, steps, 2, out, st,
+                              summary)
+            t["value"] = m / (t["ms_per_step"] * 1e-3)
+            kname = f"{name}_{label}"
+            t["roofline"] = roofline(name, m, t["phases_ms"]["search_fit"],
+                                     load_traffic(kname, digest))
+            row[label] = t
+            outs[label] = (out.cpu().numpy(), st.cpu().numpy())
         ok = (outs["fp64"][1] & 0xF) == 0
         ok &= outs["fp64"][1] == outs["mixed_refine"][1]
         err = 0.0
         for l in range(p.n_fields):
             ref = outs["fp64"][0][l][ok]
-            err = max(err, float((outs["mixed_refine"][0][l][ok] - ref).abs().max() /
-                                 ref.abs().max()))
+            err = max(err, float(np.abs(outs["mixed_refine"][0][l][ok] - ref).max() /
+                                 np.abs(ref).max()))
         row["mixed_refine_max_rel_err_vs_fp64"] = err
+        row["mixed_speedup"] = row["fp64"]["ms_per_step"] / row["mixed_refine"]["ms_per_step"]
         row["valid_targets"] = int(ok.sum())
+        if orc is not None:
+            for label in ("fp64", "mixed_refine"):
+                e, n_ok = oracle_error(orc, p, *outs[label], n_sample=2000, seed=7)
+                row[label]["max_rel_err_vs_oracle_sample"] = e
+                row[label]["oracle_sample_valid"] = n_ok
         log(f"{name}: fp64 {row['fp64']['ms_per_step']:.3f} ms, mixed_refine "
-            f"{row['mixed_refine']['ms_per_step']:.3f} ms, err {err:.2e}")
+            f"{row['mixed_refine']['ms_per_step']:.3f} ms, err vs fp64 {err:.2e}")
         rows[name] = row
         del src, vals, tgt, outs
     return rows
@@ -369,25 +475,13 @@ def main():
     rad = pcms.radius_of(p)
     prec = {"mixed": pcms.MIXED, "mixed_refine": pcms.MIXED_REFINE, "fp64": pcms.FP64}[args.precision]
 
-    def run(precision, steps, warmup, out_t):
-        o = pcms.opts(precision=precision, flags=pcms.PROFILE)
-        for _ in range(warmup):
-            pcms.pcms_mls_transfer(src, vals, tgt, p.degree, rad, p.k_cap, o=o, out=out_t, status=st)
-        torch.cuda.synchronize()
-        phases = []
-        t_start = time.perf_counter()
-        for _ in range(steps):
-            pcms.pcms_mls_transfer(src, vals, tgt, p.degree, rad, p.k_cap, o=o, out=out_t, status=st)
-            phases.append(pcms.last_phase_ms())
-        torch.cuda.synchronize()
-        t_end = time.perf_counter()
-        ms = (t_end - t_start) * 1e3 / steps
-        avg = {k: float(np.mean([ph[k] for ph in phases])) for k in phases[0]}
-        return ms, avg
-
+    summary = torch.zeros(4, dtype=torch.int32, device=dev)
     log(f"timing {args.steps} steps ({args.warmup} warm-up), precision {args.precision}")
-    ms, phases = run(prec, args.steps, args.warmup, out)
-    log(f"{ms:.3f} ms/step, phases {phases}")
+    head = time_transfer(torch, pcms, p, src, vals, tgt, rad, prec, args.steps, args.warmup, out,
+                         st, summary)
+    ms, phases = head["ms_per_step"], head["phases_ms"]
+    log(f"{ms:.3f} ms/step (event median {head['ms_median']:.3f}, min {head['ms_min']:.3f}), "
+        f"phases {phases}")
     value = M / (ms / 1e3)
     head_out = out.clone()
     status = st.cpu().numpy()
@@ -412,6 +506,7 @@ def main():
             "n_src": int(p.src.shape[0]), "n_tgt": int(M), "basis_degree": p.degree,
             "n_fields": p.n_fields, "precision": args.precision,
         },
+        "step_ms_event": {"median": head["ms_median"], "min": head["ms_min"]},
         "phases_ms": phases,
         "statuses": {"ok": int(((status & 0xF) == 0).sum()),
                      "underdetermined": int(((status & 0xF) == 1).sum()),
@@ -419,31 +514,24 @@ def main():
                      "radius_exhausted": int(((status & 0xF) == 3).sum()),
                      "capped": int(((status & 0x10) != 0).sum())},
     }
-
-    kernel_ms = phases["search_fit"]
-    achieved = ALG_FLOPS_PER_TARGET * M / (kernel_ms * 1e-3) / 1e12
-    result["roofline"] = {
-        "bound": "alu",
-        "kernel": "k_transfer (search + moment assembly + Cholesky + evaluation)",
-        "achieved": achieved,
-        "peak": VALU_PEAK_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": achieved / VALU_PEAK_TFLOPS,
-        "traffic": load_traffic(source_digest()),
-        "alg_flops_per_target": ALG_FLOPS_PER_TARGET,
-        "kernel_ms": kernel_ms,
-    }
+    result["roofline"] = roofline("c3", M, phases["search_fit"],
+                                  load_traffic(f"c3_{args.precision}", source_digest()))
 
     if not args.no_fp64 and prec != pcms.FP64:
         out64 = torch.empty_like(out)
-        ms64, ph64 = run(pcms.FP64, args.steps, 1, out64)
+        t64 = time_transfer(torch, pcms, p, src, vals, tgt, rad, pcms.FP64, args.steps, 1, out64,
+                            st, summary)
+        ms64, ph64 = t64["ms_per_step"], t64["phases_ms"]
         ok = torch.from_numpy((status & 0xF) == 0).to(dev)
         err = 0.0
         for l in range(p.n_fields):
             ref = out64[l][ok]
             err = max(err, float((head_out[l][ok] - ref).abs().max() / ref.abs().max()))
         result["fp64"] = {"value": M / (ms64 / 1e3), "ms_per_step": ms64, "phases_ms": ph64,
-                          "mixed_speedup": ms64 / ms}
+                          "step_ms_event": {"median": t64["ms_median"], "min": t64["ms_min"]},
+                          "mixed_speedup": ms64 / ms,
+                          "roofline": roofline("c3", M, ph64["search_fit"],
+                                               load_traffic("c3_fp64", source_digest()))}
         result["accuracy"] = {"max_rel_err_vs_fp64_all_targets": err}
         log(f"fp64 {ms64:.3f} ms/step; headline vs fp64 max rel err {err:.3e}")
 
@@ -500,10 +588,16 @@ def main():
 
     if not args.no_batch:
         del head_out, out
-        result["batched"] = batched_leg(torch, pcms, synth, dev, args.steps)
+        orc_b = None
+        if not args.no_cpu:
+            import oracle as orc_b
+        result["batched"] = batched_leg(torch, pcms, synth, dev, args.steps, orc_b)
 
     if not args.no_configs:
-        result["other_configs"] = configs_leg(torch, pcms, synth, dev, args.steps)
+        orc = None
+        if not args.no_cpu:
+            import oracle as orc
+        result["other_configs"] = configs_leg(torch, pcms, synth, dev, args.steps, orc)
 
     print(json.dumps(result), flush=True)
 

@@ -90,12 +90,18 @@ typedef struct {
 } pcms_radius;
 
 /* Radial weights phi(q), q = sqrt(D) / r (Table 1 of the paper, shape
- * parameter a = 2, plus Wendland C2 (1-q)^4 (4q+1), the default). */
+ * parameter a = 2, plus Wendland C2 (1-q)^4 (4q+1), the default).  Table 1's
+ * No_Op (identity, phi = 1 everywhere) weighs the selected sources exactly as
+ * Const (phi = 1 inside the radius): only sources strictly inside the radius
+ * enter the fit, so the two give the same results.  Multiquadric, thin plate
+ * spline and cubic spline are not positive and decreasing on [0, 1) and are
+ * not offered as least-squares weights. */
 #define PCMS_WEIGHT_WENDLAND_C2 0
 #define PCMS_WEIGHT_C4 1
 #define PCMS_WEIGHT_GAUSSIAN 2
 #define PCMS_WEIGHT_CONST 3
 #define PCMS_WEIGHT_IMQ 4
+#define PCMS_WEIGHT_NO_OP 5
 
 /* Arithmetic of the moment assembly.
  *   FP64:         everything in FP64.
@@ -322,8 +328,9 @@ pcms_status pcms_autotune(const pcms_problem *sample, int32_t n, const pcms_batc
  * arguments, checks, results and return codes as pcms_mls_transfer_grid,
  * but the call allocates nothing (no hipMalloc, hipMallocAsync, hipFree or
  * event creation): its workspace -- status counts, target order, sort
- * buffers and bucket-ordered field records, about
- * 8 * n_src * (n_fields rounded up to even) + 28 * n_tgt bytes -- is a fixed
+ * buffers, bucket-ordered field records and staged outputs, about
+ * 8 * (n_src + n_tgt) * (n_fields rounded up to even) + 28 * n_tgt bytes --
+ * is a fixed
  * device array of PCMS_NOALLOC_SCRATCH_BYTES per GPU, which the library holds
  * from the moment it is loaded on that GPU until the process ends.  A call
  * needing more returns PCMS_ERR_ARG before any HIP call.  PCMS_PROFILE is
@@ -341,13 +348,49 @@ pcms_status pcms_mls_transfer_grid_noalloc(const pcms_grid *grid, const double *
 /* PCMS_NOALLOC_SCRATCH_BYTES as built into the library. */
 size_t pcms_noalloc_scratch_bytes(void);
 
+/* ---------------------------------------------------------------------- */
+/* Work-space sizes.                                                       */
+/* ---------------------------------------------------------------------- */
+
+/* Device memory of a problem of n_src sources of dimension dim, n_fields
+ * fields and n_tgt targets, in bytes.  The library's temporary buffers come
+ * from the HIP stream-ordered pool of the current device (hipMallocAsync,
+ * which keeps freed blocks cached); callers that reserve that pool, or
+ * choose between the allocating and the allocation-free calls, size it from
+ * these figures. */
+typedef struct {
+    size_t grid_bytes;           /* a pcms_grid (held until pcms_grid_free) */
+    size_t grid_build_bytes;     /* temporary, during pcms_grid_build */
+    size_t transfer_bytes;       /* peak temporary of pcms_mls_transfer */
+    size_t transfer_grid_bytes;  /* temporary of pcms_mls_transfer_grid (the
+                                    work space pcms_mls_transfer_grid_noalloc
+                                    needs, <= noalloc_limit to be accepted) */
+    size_t operator_apply_bytes; /* temporary of pcms_operator_apply */
+    size_t noalloc_limit;        /* PCMS_NOALLOC_SCRATCH_BYTES */
+} pcms_workspace;
+
+/* Fills *out (host) for the given sizes; host-only arithmetic, no HIP call.
+ * PCMS_ERR_ARG for dim outside 1..5, n_src outside [1, 2^30), n_tgt outside
+ * [0, 2^30) or n_fields < 1. */
+pcms_status pcms_workspace_query(int64_t n_src, int32_t dim, int32_t n_fields, int64_t n_tgt,
+                                 pcms_workspace *out);
+
 /* Phase times in milliseconds of the calling thread's last call made with
  * PCMS_PROFILE, measured with HIP events on that call's stream: [0] grid
  * build, [1] target ordering, [2] field gather into bucket order, [3] the
- * search-and-fit kernel.  Writes min(n, 4) entries to the host array `ms`
- * and returns that count (0 if no profiled call was made).  A profiled call
- * synchronises its stream before returning. */
+ * search-and-fit kernel, [4] the transpose of the outputs into field-major
+ * order.  Writes min(n, 5) entries to the host array `ms` and returns that
+ * count (0 if no profiled call was made).  A profiled call does not wait for
+ * its events: they are read when a later profiled call has been enqueued,
+ * or here (which waits for them). */
 int32_t pcms_last_phase_ms(float *ms, int32_t n);
+
+/* Sums of the phase times (as above) over every profiled call of the
+ * calling thread since the last reset, into the host array sum_ms[min(n,
+ * 5)] (may be NULL); returns the number of calls summed (-1 on a HIP
+ * error).  Waits for the pending events.  reset != 0 clears the sums after
+ * reading them. */
+int32_t pcms_phase_ms_sum(double *sum_ms, int32_t n, int32_t reset);
 
 /* Library version (major*10000 + minor*100 + patch) and the calling
  * thread's last error message ("" if none). */

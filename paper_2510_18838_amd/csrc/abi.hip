@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -67,7 +68,7 @@ pcms_status check_scale(const double *g, int dim)
 pcms_status check_opts(const pcms_mls_opts *o)
 {
     if (!o) return PCMS_OK;
-    if (o->weight < PCMS_WEIGHT_WENDLAND_C2 || o->weight > PCMS_WEIGHT_IMQ)
+    if (o->weight < PCMS_WEIGHT_WENDLAND_C2 || o->weight > PCMS_WEIGHT_NO_OP)
         return arg_error("unknown weight function");
     if (o->precision < PCMS_FP64 || o->precision > PCMS_MIXED_REFINE)
         return arg_error("unknown precision");
@@ -164,45 +165,87 @@ pcms_status finish(const int32_t *summary_dev, bool async, hipStream_t s, bool j
 std::once_flag g_pool_once[64];
 
 // Phase timing with HIP events (PCMS_PROFILE).
-constexpr int kPhases = 4;
+// Phase timing with HIP events (PCMS_PROFILE).  A profiled call records
+// kPhases + 1 events on its stream and does not wait for them: its times are
+// read once a later profiled call has been enqueued (so the device always has
+// queued work), or when they are queried.  Two event sets alternate.
+constexpr int kPhases = 5;
+struct EventSet {
+    hipEvent_t ev[kPhases + 1] = {};
+    bool have[kPhases + 1] = {};
+    bool pending = false;
+};
 struct Profiler {
     bool on = false;
     hipStream_t s = nullptr;
-    hipEvent_t ev[kPhases + 1] = {};
-    bool have[kPhases + 1] = {};
+    EventSet set[2];
+    int cur = 0;
+    float last[kPhases] = {};
+    double sum[kPhases] = {};
+    int n_last = 0, calls = 0;
+
     pcms_status mark(int i)
     {
         if (!on) return PCMS_OK;
-        if (!ev[i]) PCMS_HIP(hipEventCreate(&ev[i]));
-        PCMS_HIP(hipEventRecord(ev[i], s));
-        have[i] = true;
+        EventSet &e = set[cur];
+        if (!e.ev[i]) PCMS_HIP(hipEventCreate(&e.ev[i]));
+        PCMS_HIP(hipEventRecord(e.ev[i], s));
+        e.have[i] = true;
         return PCMS_OK;
+    }
+    // Waits for a pending set and adds its phase times to the statistics.
+    pcms_status resolve(int k)
+    {
+        EventSet &e = set[k];
+        if (!e.pending) return PCMS_OK;
+        e.pending = false;
+        int lastev = -1;
+        for (int i = kPhases; i >= 0 && lastev < 0; --i)
+            if (e.have[i]) lastev = i;
+        if (lastev < 0) return PCMS_OK;
+        PCMS_HIP(hipEventSynchronize(e.ev[lastev]));
+        for (int i = 0; i < kPhases; ++i) {
+            float ms = 0.0f;
+            if (e.have[i] && e.have[i + 1]) PCMS_HIP(hipEventElapsedTime(&ms, e.ev[i], e.ev[i + 1]));
+            last[i] = ms;
+            sum[i] += ms;
+        }
+        n_last = kPhases;
+        ++calls;
+        return PCMS_OK;
+    }
+    pcms_status resolve_all()
+    {
+        const int older = cur ^ 1;
+        pcms_status st = resolve(older);
+        if (st != PCMS_OK) return st;
+        return resolve(cur);
     }
 };
 thread_local Profiler g_prof;
-thread_local float g_phase_ms[kPhases] = {0, 0, 0, 0};
-thread_local int g_phase_n = 0;
 
 pcms_status profile_begin(const pcms_mls_opts *o, hipStream_t s)
 {
     g_prof.on = o && (o->flags & PCMS_PROFILE);
+    if (!g_prof.on) return PCMS_OK;
+    g_prof.cur ^= 1;
+    // the set about to be reused belongs to the call before the previous one
+    pcms_status st = g_prof.resolve(g_prof.cur);
+    if (st != PCMS_OK) return st;
     g_prof.s = s;
-    for (bool &h : g_prof.have) h = false;
+    for (bool &h : g_prof.set[g_prof.cur].have) h = false;
     return g_prof.mark(0);
 }
 
+// After the call's work is enqueued: its events are pending, and the
+// previous call's times are read (that call has completed or is completing
+// ahead of this one on the device).
 pcms_status profile_end()
 {
     if (!g_prof.on) return PCMS_OK;
-    PCMS_HIP(hipEventSynchronize(g_prof.ev[kPhases]));
-    for (int i = 0; i < kPhases; ++i) {
-        float ms = 0.0f;
-        if (g_prof.have[i] && g_prof.have[i + 1]) PCMS_HIP(hipEventElapsedTime(&ms, g_prof.ev[i], g_prof.ev[i + 1]));
-        g_phase_ms[i] = ms;
-    }
-    g_phase_n = kPhases;
+    g_prof.set[g_prof.cur].pending = true;
     g_prof.on = false;
-    return PCMS_OK;
+    return g_prof.resolve(g_prof.cur ^ 1);
 }
 
 }  // namespace
@@ -242,18 +285,35 @@ void scratch_free(void *p, hipStream_t s)
 
 namespace {
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
-// workspace of a transfer on a grid: [summary | tperm | svals | sort buffers]
+// workspace of a transfer on a grid:
+// [summary | tperm | svals | staged outputs | sort buffers]
 struct TransferWs {
-    size_t off_tperm, off_svals, off_sort, bytes;
+    size_t off_tperm, off_svals, off_stage, off_sort, bytes;
     TransferWs(int64_t n_src, int n_fields, int64_t n_tgt)
     {
         off_tperm = 256;
         off_svals = off_tperm + align256(sizeof(int) * (size_t)n_tgt);
-        off_sort = off_svals + align256(sizeof(double) * (size_t)n_src * padded_dim(n_fields));
+        off_stage = off_svals + align256(sizeof(double) * (size_t)n_src * padded_dim(n_fields));
+        off_sort = off_stage + align256(sizeof(double) * (size_t)n_tgt * padded_dim(n_fields));
         bytes = off_sort + sort_targets_bytes(n_tgt);
     }
 };
 }  // namespace
+
+// Arrays of a grid over n_src sources: parameters, cell starts, both
+// permutations, FP64 and FP32 coordinate records.
+struct GridLayout {
+    size_t o_cs, o_perm, o_iperm, o_spts, o_s32, bytes;
+    GridLayout(int64_t n_src, int dim)
+    {
+        o_cs = 256;
+        o_perm = o_cs + align256(sizeof(int) * ((size_t)cells_cap_for(n_src) + 1));
+        o_iperm = o_perm + align256(sizeof(int) * (size_t)n_src);
+        o_spts = o_iperm + align256(sizeof(int) * (size_t)n_src);
+        o_s32 = o_spts + align256(sizeof(double) * (size_t)n_src * padded_dim(dim));
+        bytes = o_s32 + sizeof(float) * (size_t)n_src * padded_dim32(dim);
+    }
+};
 
 size_t transfer_ws_bytes(int64_t n_src, int n_fields, int64_t n_tgt)
 {
@@ -280,6 +340,7 @@ pcms_status transfer_on_grid(const Grid *g, const double *src_vals, int32_t n_fi
     int32_t *summary = async ? o.summary : (int32_t *)ws;
     int *tperm = (int *)((char *)ws + L.off_tperm);
     double *svals = (double *)((char *)ws + L.off_svals);
+    double *stage = (double *)((char *)ws + L.off_stage);
     if ((st = zero_ints(summary, 4, s)) != PCMS_OK) return st;
     if ((st = g_prof.mark(1)) != PCMS_OK) return st;
     if ((st = sort_targets(g, tgt, n_tgt, tperm, s, (char *)ws + L.off_sort)) != PCMS_OK) return st;
@@ -288,9 +349,11 @@ pcms_status transfer_on_grid(const Grid *g, const double *src_vals, int32_t n_fi
     if ((st = g_prof.mark(3)) != PCMS_OK) return st;
     LaunchSpec ls{g, tgt, tperm, n_tgt, *radius, k_cap, o.block, summary};
     st = launch_transfer(ls, svals, n_fields, degree, o.weight, o.precision, o.lambda, tgt_vals,
-                         status, s);
+                         stage, status, s);
     if (st != PCMS_OK) return st;
     if ((st = g_prof.mark(4)) != PCMS_OK) return st;
+    if ((st = unstage_fields(stage, n_tgt, n_fields, tgt_vals, s)) != PCMS_OK) return st;
+    if ((st = g_prof.mark(5)) != PCMS_OK) return st;
     if ((st = profile_end()) != PCMS_OK) return st;
     return finish(summary, async, s, true);
 }
@@ -333,9 +396,23 @@ int32_t pcms_version(void) { return 100; }
 int32_t pcms_last_phase_ms(float *ms, int32_t n)
 {
     if (!ms || n <= 0) return 0;
-    int c = n < g_phase_n ? n : g_phase_n;
-    for (int i = 0; i < c; ++i) ms[i] = g_phase_ms[i];
+    if (g_prof.resolve_all() != PCMS_OK) return 0;
+    int c = n < g_prof.n_last ? n : g_prof.n_last;
+    for (int i = 0; i < c; ++i) ms[i] = g_prof.last[i];
     return c;
+}
+
+int32_t pcms_phase_ms_sum(double *sum_ms, int32_t n, int32_t reset)
+{
+    if (g_prof.resolve_all() != PCMS_OK) return -1;
+    const int calls = g_prof.calls;
+    if (sum_ms)
+        for (int i = 0; i < n && i < kPhases; ++i) sum_ms[i] = g_prof.sum[i];
+    if (reset) {
+        for (double &x : g_prof.sum) x = 0.0;
+        g_prof.calls = 0;
+    }
+    return calls;
 }
 
 const char *pcms_last_error(void) { return g_last_error.c_str(); }
@@ -425,6 +502,28 @@ pcms_status pcms_neighbors(const pcms_grid *grid, const double *tgt, int64_t n_t
     return finish(summary, false, s, false);
 }
 
+pcms_status pcms_workspace_query(int64_t n_src, int32_t dim, int32_t n_fields, int64_t n_tgt,
+                                 pcms_workspace *out)
+{
+    if (!out) return arg_error("out is NULL");
+    if (dim < 1 || dim > kMaxDim) return arg_error("dim must be in [1, 5]");
+    if (n_src < 1 || n_src >= ((int64_t)1 << 31) / 2) return arg_error("n_src must be in [1, 2^30)");
+    if (n_tgt < 0 || n_tgt >= ((int64_t)1 << 31) / 2) return arg_error("n_tgt must be in [0, 2^30)");
+    if (n_fields < 1) return arg_error("n_fields must be >= 1");
+    const GridLayout G(n_src, dim);
+    const size_t build = grid_build_scratch_bytes(n_src);
+    const size_t xfer = transfer_ws_bytes(n_src, n_fields, n_tgt);
+    out->grid_bytes = G.bytes;
+    out->grid_build_bytes = build;
+    out->transfer_grid_bytes = xfer;
+    // the one-shot call keeps its grid for the whole call; the build's
+    // scratch is released (stream-ordered) before the transfer's is taken
+    out->transfer_bytes = G.bytes + std::max(build, xfer);
+    out->operator_apply_bytes = sizeof(double) * (size_t)n_src * padded_dim(n_fields);
+    out->noalloc_limit = PCMS_NOALLOC_SCRATCH_BYTES;
+    return PCMS_OK;
+}
+
 pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, const double *src_vals,
                               int32_t n_fields, const double *tgt, int64_t n_tgt,
                               int32_t basis_degree, const pcms_radius *radius, int32_t k_cap,
@@ -451,19 +550,14 @@ pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, con
     PCMS_HIP(hipGetDevice(&g.device));
     Scratch sc;
     sc.s = s;
-    size_t o_cs = 256;
-    size_t o_perm = o_cs + ((sizeof(int) * ((size_t)g.n_cells_cap + 1) + 255) & ~(size_t)255);
-    size_t o_iperm = o_perm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
-    size_t o_spts = o_iperm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
-    size_t o_s32 = o_spts + ((sizeof(double) * (size_t)n_src * padded_dim(dim) + 255) & ~(size_t)255);
-    size_t bytes = o_s32 + sizeof(float) * (size_t)n_src * padded_dim32(dim);
-    if ((st = scratch_alloc(&sc.p, bytes, s)) != PCMS_OK) return st;
+    const GridLayout L(n_src, dim);
+    if ((st = scratch_alloc(&sc.p, L.bytes, s)) != PCMS_OK) return st;
     g.params = (GridParams *)sc.p;
-    g.cell_start = (int *)((char *)sc.p + o_cs);
-    g.perm = (int *)((char *)sc.p + o_perm);
-    g.iperm = (int *)((char *)sc.p + o_iperm);
-    g.spts = (double *)((char *)sc.p + o_spts);
-    g.spts32 = (float *)((char *)sc.p + o_s32);
+    g.cell_start = (int *)((char *)sc.p + L.o_cs);
+    g.perm = (int *)((char *)sc.p + L.o_perm);
+    g.iperm = (int *)((char *)sc.p + L.o_iperm);
+    g.spts = (double *)((char *)sc.p + L.o_spts);
+    g.spts32 = (float *)((char *)sc.p + L.o_s32);
     if ((st = build_grid_device(&g, src, cw, ppc, s)) != PCMS_OK) return st;
     return transfer_on_grid(&g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts,
                             s, tgt_vals, status, nullptr);

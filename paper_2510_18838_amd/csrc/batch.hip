@@ -510,7 +510,7 @@ pcms_status batch_enqueue(BatchPlan &p, hipStream_t s)
         pcms_radius r{B.mode, B.k, B.n_min, B.max_iter, B.r};
         LaunchSpec ls{&p.views[q], B.tgt, p.tperm + B.tgt_off, B.n_tgt, r, B.k_cap, p.block, p.summary};
         st = launch_transfer(ls, p.svals + B.sval_off, B.nf, B.degree, p.weight, p.precision, p.lambda,
-                             B.out, B.status, s);
+                             B.out, nullptr, B.status, s);
         if (st != PCMS_OK) return st;
     }
     return PCMS_OK;

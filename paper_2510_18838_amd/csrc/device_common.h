@@ -248,6 +248,17 @@ PCMS_HD PCMS_INLINE void load_pair(const double *__restrict__ p, double &x, doub
 #endif
 }
 
+// Two consecutive doubles to a 16-byte aligned address, in one store.
+PCMS_HD PCMS_INLINE void store_pair(double *__restrict__ p, double x, double y)
+{
+#ifdef PCMS_HOST_EMULATION
+    p[0] = x;
+    p[1] = y;
+#else
+    *reinterpret_cast<double2 *>(p) = make_double2(x, y);
+#endif
+}
+
 // Atomic add to a word of the block's LDS.
 PCMS_HD PCMS_INLINE void lds_add(int *w, int v)
 {

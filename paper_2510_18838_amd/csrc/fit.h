@@ -70,7 +70,8 @@ PCMS_HD PCMS_INLINE T weight_in(int kind, T q, T o)
         return poly * o6;
     }
     case PCMS_WEIGHT_GAUSSIAN: return exp(-(T(2) * q) * (T(2) * q));
-    case PCMS_WEIGHT_CONST: return T(1);
+    case PCMS_WEIGHT_CONST:
+    case PCMS_WEIGHT_NO_OP: return T(1);
     case PCMS_WEIGHT_IMQ: return T(1) / sqrt(T(1) + (T(2) * q) * (T(2) * q));
     default: {
         T o2 = o * o;
@@ -180,6 +181,10 @@ struct KArgs {
     int weight;
     double lambda;
     double *out;           // [nf][n_tgt]
+    double *stage;         // [n_tgt][nfs] by original target index, or NULL: the
+                           // fields of a target are written as one record
+                           // (whole 16-byte words) and transposed into out by a
+                           // later kernel, instead of nf scattered 8-byte stores
     // operator emission only: [width][n_tgt] weights and source indices, counts
     double *op_w;
     int32_t *op_c;
@@ -383,17 +388,26 @@ PCMS_HD PCMS_INLINE void field_pass(S_ &S, const KArgs &a, const GridParams &gp,
     }
 }
 
-// Group sums of a field chunk, written to the target's outputs.
+// Group sums of a field chunk, written to the target's outputs (or to its
+// staged record, whose padding past nf receives zeros).
 template <int G>
 PCMS_HD PCMS_INLINE void write_fields(const KArgs &a, int ti, int l0,
                                       const double (&acc)[kFieldChunk],
                                       const double (&fref)[kFieldChunk], Grp<G> g)
 {
+    double v[kFieldChunk];
 #pragma unroll
-    for (int l = 0; l < kFieldChunk; ++l) {
-        const double v = g.sum(acc[l]) + fref[l];
-        if (l0 + l < a.nf && (l % G) == g.q) a.out[(size_t)(l0 + l) * a.n_tgt + ti] = v;
+    for (int l = 0; l < kFieldChunk; ++l) v[l] = g.sum(acc[l]) + fref[l];
+    if (a.stage) {
+        double *rec = a.stage + (size_t)ti * a.nfs + l0;
+#pragma unroll
+        for (int h = 0; h < kFieldChunk / 2; ++h)
+            if (l0 + 2 * h < a.nfs && (h % G) == g.q) store_pair(rec + 2 * h, v[2 * h], v[2 * h + 1]);
+        return;
     }
+#pragma unroll
+    for (int l = 0; l < kFieldChunk; ++l)
+        if (l0 + l < a.nf && (l % G) == g.q) a.out[(size_t)(l0 + l) * a.n_tgt + ti] = v[l];
 }
 
 // Field transfer of the target at sorted slot i; returns its status.
@@ -566,7 +580,12 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
     if (EMIT) {
         if (g.q == 0) a.op_n[i] = (st & 0xF) == PCMS_TGT_OK ? n : -1;
     } else if ((st & 0xF) != PCMS_TGT_OK) {
-        for (int l = g.q; l < a.nf; l += G) a.out[(size_t)l * a.n_tgt + ti] = NAN;
+        if (a.stage) {
+            for (int h = g.q; 2 * h < a.nfs; h += G)
+                store_pair(a.stage + (size_t)ti * a.nfs + 2 * h, NAN, NAN);
+        } else {
+            for (int l = g.q; l < a.nf; l += G) a.out[(size_t)l * a.n_tgt + ti] = NAN;
+        }
     }
     if (a.status && g.q == 0) a.status[ti] = (uint8_t)st;
     return st;

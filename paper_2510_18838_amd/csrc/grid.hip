@@ -384,6 +384,22 @@ __global__ void k_scatter_vals(const double *__restrict__ vals, const int *__res
     }
 }
 
+// out[l][t] = stage[t][l] for l < nf: each thread reads its target's record
+// in 16-byte words and writes one coalesced element per field.
+__global__ void k_unstage(const double *__restrict__ stage, int64_t n, int nf, int nfs,
+                          double *__restrict__ out)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const double *rec = stage + t * nfs;
+        for (int l = 0; l < nf; l += 2) {
+            const double2 v = *reinterpret_cast<const double2 *>(rec + l);
+            out[(int64_t)l * n + t] = v.x;
+            if (l + 1 < nf) out[(int64_t)(l + 1) * n + t] = v.y;
+        }
+    }
+}
+
 int grid_blocks(int64_t n, int tpb)
 {
     int64_t b = (n + tpb - 1) / tpb;
@@ -398,13 +414,18 @@ int cells_cap_for(int64_t n_src)
     return (int)std::min<int64_t>(c, (int64_t)1 << 30);
 }
 
+size_t grid_build_scratch_bytes(int64_t n_src)
+{
+    // bbox keys + metric copy + sort buffers
+    return 256 + sort_scratch_bytes((int)n_src) + 64 * sizeof(double);
+}
+
 pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
                               double pts_per_cell, hipStream_t s)
 {
     const int dim = grid->dim;
     const int n = (int)grid->n_src;
-    // scratch: bbox keys + metric copy + sort buffers
-    size_t bytes = 256 + sort_scratch_bytes(n) + 64 * sizeof(double);
+    size_t bytes = grid_build_scratch_bytes(n);
     void *raw = nullptr;
     pcms_status st = scratch_alloc(&raw, bytes, s);
     if (st != PCMS_OK) return st;
@@ -509,6 +530,15 @@ int bits_for(double bound)
     int b = 0;
     while (b < 32 && (double)(1ull << b) < bound) ++b;
     return b;
+}
+
+pcms_status unstage_fields(const double *stage, int64_t n_tgt, int n_fields, double *out,
+                           hipStream_t s)
+{
+    k_unstage<<<grid_blocks(n_tgt, 256), 256, 0, s>>>(stage, n_tgt, n_fields,
+                                                      padded_dim(n_fields), out);
+    PCMS_HIP(hipGetLastError());
+    return PCMS_OK;
 }
 
 pcms_status gather_values(const Grid *grid, const double *vals, int n_fields, double *svals,

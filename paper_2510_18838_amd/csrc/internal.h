@@ -47,12 +47,17 @@ int cells_cap_for(int64_t n_src);
 // cell_width > 0: metric bucket width; else buckets sized for pts_per_cell.
 pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
                               double pts_per_cell, hipStream_t s);
+// Stream-ordered scratch that build_grid_device takes while it runs.
+size_t grid_build_scratch_bytes(int64_t n_src);
 // Target ordering: tperm[i] = index of the target at sorted position i.  Its
 // sort buffers are `ws` (sort_targets_bytes(n_tgt) bytes, 256-byte aligned)
 // when given, else stream-ordered scratch.
 size_t sort_targets_bytes(int64_t n_tgt);
 pcms_status sort_targets(const Grid *grid, const double *tgt, int64_t n_tgt, int *tperm,
                          hipStream_t s, void *ws = nullptr);
+// out[l][t] = stage[t * padded_dim(n_fields) + l] for l < n_fields.
+pcms_status unstage_fields(const double *stage, int64_t n_tgt, int n_fields, double *out,
+                           hipStream_t s);
 // Sorted field copy: svals[p * n_fields + l] = vals[l * n_src + perm[p]].
 pcms_status gather_values(const Grid *grid, const double *vals, int n_fields, double *svals,
                           hipStream_t s);
@@ -102,9 +107,10 @@ struct LaunchSpec {
 pcms_status launch_neighbors(const LaunchSpec &ls, int32_t *nbr, int32_t *n_kept,
                              int32_t *n_found, double *r2, uint8_t *status, hipStream_t s);
 
+// stage: NULL, or [n_tgt][padded_dim(n_fields)] records for unstage_fields.
 pcms_status launch_transfer(const LaunchSpec &ls, const double *svals, int n_fields, int degree,
                             int weight, int precision, double lambda, double *out,
-                            uint8_t *status, hipStream_t s);
+                            double *stage, uint8_t *status, hipStream_t s);
 
 pcms_status zero_ints(int32_t *p, int n, hipStream_t s);
 

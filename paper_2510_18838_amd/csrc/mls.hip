@@ -130,7 +130,7 @@ pcms_status launch_neighbors(const LaunchSpec &ls, int32_t *nbr, int32_t *n_kept
 
 pcms_status launch_transfer(const LaunchSpec &ls, const double *svals, int n_fields, int degree,
                             int weight, int precision, double lambda, double *out,
-                            uint8_t *status, hipStream_t s)
+                            double *stage, uint8_t *status, hipStream_t s)
 {
     if (ls.n_tgt == 0) return PCMS_OK;
     const int block = pick_block(ls.block, ls);
@@ -141,6 +141,7 @@ pcms_status launch_transfer(const LaunchSpec &ls, const double *svals, int n_fie
     a.weight = weight;
     a.lambda = lambda;
     a.out = out;
+    a.stage = stage;
     a.status = status;
     KernelFn fn = xfer_for(ls.grid->dim, degree, precision, unit_metric(ls.grid));
     const int launch = ((a.n_blocks + 7) / 8) * 8;

@@ -79,7 +79,7 @@ pcms_status pcms_mls_transfer_grid_noalloc(const pcms_grid *grid, const double *
     if (need > kScratchBytes) {
         set_error("the transfer needs " + std::to_string(need) + " bytes of workspace, more than "
                   "the " + std::to_string(kScratchBytes) + " of the allocation-free entry point "
-                  "(about 8 * n_src * (n_fields rounded up to even) + 28 * n_tgt bytes)");
+                  "(about 8 * (n_src + n_tgt) * (n_fields rounded up to even) + 28 * n_tgt bytes)");
         return PCMS_ERR_ARG;
     }
     if (n_tgt == 0) return PCMS_OK;

@@ -27,7 +27,7 @@ PCMS_ERR_RADIUS_EXHAUSTED = 6
 
 TGT_OK, TGT_UNDERDETERMINED, TGT_SINGULAR, TGT_RADIUS_EXHAUSTED, TGT_CAPPED = 0, 1, 2, 3, 0x10
 RADIUS_FIXED, RADIUS_KNN, RADIUS_GROW = 0, 1, 2
-WEIGHT_WENDLAND_C2, WEIGHT_C4, WEIGHT_GAUSSIAN, WEIGHT_CONST, WEIGHT_IMQ = 0, 1, 2, 3, 4
+WEIGHT_WENDLAND_C2, WEIGHT_C4, WEIGHT_GAUSSIAN, WEIGHT_CONST, WEIGHT_IMQ, WEIGHT_NO_OP = range(6)
 FP64, MIXED, MIXED_REFINE = 0, 1, 2
 ASYNC = 0x1
 PROFILE = 0x2
@@ -38,7 +38,7 @@ EXPORTED = ("pcms_mls_opts_default", "pcms_grid_build", "pcms_grid_free", "pcms_
             "pcms_batch_plan_exec", "pcms_batch_plan_free", "pcms_autotune",
             "pcms_operator_build", "pcms_operator_apply", "pcms_operator_export",
             "pcms_operator_width", "pcms_operator_free", "pcms_mls_transfer_grid_noalloc",
-            "pcms_noalloc_scratch_bytes")
+            "pcms_noalloc_scratch_bytes", "pcms_workspace_query", "pcms_phase_ms_sum")
 
 
 class PcmsError(RuntimeError):
@@ -70,6 +70,12 @@ class BatchOpts(ctypes.Structure):
     _fields_ = [("weight", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("lam", ctypes.c_double), ("block", ctypes.c_int32),
                 ("cell_factor", ctypes.c_double), ("tune_cache", ctypes.c_char_p)]
+
+
+class Workspace(ctypes.Structure):
+    _fields_ = [("grid_bytes", ctypes.c_size_t), ("grid_build_bytes", ctypes.c_size_t),
+                ("transfer_bytes", ctypes.c_size_t), ("transfer_grid_bytes", ctypes.c_size_t),
+                ("operator_apply_bytes", ctypes.c_size_t), ("noalloc_limit", ctypes.c_size_t)]
 
 
 class TuneResult(ctypes.Structure):
@@ -107,10 +113,14 @@ def lib() -> ctypes.CDLL:
     L.pcms_mls_transfer_grid.restype = i32
     L.pcms_mls_transfer_grid_noalloc.argtypes = L.pcms_mls_transfer_grid.argtypes
     L.pcms_mls_transfer_grid_noalloc.restype = i32
+    L.pcms_workspace_query.argtypes = [i64, i32, i32, i64, ctypes.POINTER(Workspace)]
+    L.pcms_workspace_query.restype = i32
     L.pcms_noalloc_scratch_bytes.argtypes = []
     L.pcms_noalloc_scratch_bytes.restype = ctypes.c_size_t
     L.pcms_last_phase_ms.argtypes = [P, i32]
     L.pcms_last_phase_ms.restype = i32
+    L.pcms_phase_ms_sum.argtypes = [P, i32, i32]
+    L.pcms_phase_ms_sum.restype = i32
     L.pcms_version.argtypes = []
     L.pcms_version.restype = i32
     L.pcms_last_error.argtypes = []
@@ -146,14 +156,24 @@ def last_error() -> str:
     return lib().pcms_last_error().decode()
 
 
-PHASES = ("grid_build", "target_order", "field_gather", "search_fit")
+PHASES = ("grid_build", "target_order", "field_gather", "search_fit", "output_transpose")
 
 
 def last_phase_ms() -> dict:
     """Phase times (ms) of this thread's last call made with the PROFILE flag."""
-    buf = (ctypes.c_float * 4)()
-    n = lib().pcms_last_phase_ms(ctypes.cast(buf, ctypes.c_void_p), 4)
+    buf = (ctypes.c_float * len(PHASES))()
+    n = lib().pcms_last_phase_ms(ctypes.cast(buf, ctypes.c_void_p), len(PHASES))
     return {PHASES[i]: float(buf[i]) for i in range(n)}
+
+
+def phase_ms_sum(reset: bool = True):
+    """(calls, {phase: summed ms}) over this thread's profiled calls since the
+    last reset."""
+    buf = (ctypes.c_double * len(PHASES))()
+    n = lib().pcms_phase_ms_sum(ctypes.cast(buf, ctypes.c_void_p), len(PHASES), int(reset))
+    if n < 0:
+        raise PcmsError(PCMS_ERR_HIP, last_error())
+    return n, {PHASES[i]: float(buf[i]) for i in range(len(PHASES))}
 
 
 def _check(code: int, allow=()):
@@ -368,6 +388,14 @@ def pcms_mls_transfer_grid_noalloc(grid: Grid, src_vals: torch.Tensor, tgt: torc
                                                        _stream(stream), _ptr(out), _ptr(status)),
                   allow)
     return out, status, code
+
+
+def pcms_workspace_query(n_src: int, dim: int, n_fields: int, n_tgt: int) -> dict:
+    """Device bytes the calls take for a problem of these sizes (host-only)."""
+    w = Workspace()
+    _check(lib().pcms_workspace_query(int(n_src), int(dim), int(n_fields), int(n_tgt),
+                                      ctypes.byref(w)))
+    return {name: int(getattr(w, name)) for name, _ in Workspace._fields_}
 
 
 def noalloc_scratch_bytes() -> int:

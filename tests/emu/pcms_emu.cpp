@@ -304,6 +304,10 @@ int main(int argc, char **argv)
     a.op_c = op_c.data();
     a.op_n = op_n.data();
     a.out = out.data();
+    // transfers stage each target's fields as one record, as the one-problem
+    // launches do (poisoned: every record must be written in full)
+    std::vector<double> stage((size_t)n_tgt * a.nfs, -777.0);
+    if (op == 1) a.stage = stage.data();
     a.nbr = nbr.data();
     a.n_kept = n_kept.data();
     a.n_found = n_found.data();
@@ -320,6 +324,15 @@ int main(int argc, char **argv)
         default: die("bad dim");
     }
 #undef DIMCASE
+    if (op == 1) {
+        // the output transpose of the staged records
+        for (int64_t t = 0; t < n_tgt; ++t)
+            for (int l = 0; l < a.nfs; ++l) {
+                const double v = stage[(size_t)t * a.nfs + l];
+                if (v == -777.0) die("staged record not written in full");
+                if (l < nf) out[(size_t)l * n_tgt + t] = v;
+            }
+    }
     std::fprintf(stderr, "work: walks %lld rows %lld candidates %lld per target: %.2f %.2f %.2f"
                  " exact rechecks %.3f\n",
                  g_walks, g_rows, g_cands, (double)g_walks / n_tgt, (double)g_rows / n_tgt,

@@ -70,8 +70,14 @@ def check_lists(be, prob, where, brute=False):
     return ref
 
 
+# Table 1's No_Op (identity) weight is phi = 1; on the selected sources, the
+# only ones that enter the fit, it is the Const weight
+NO_OP, CONST = 5, 3
+
+
 def check_transfer(be, prob, where, precisions=(FP64, MIXED_REFINE, MIXED), weight=0, lam=0.0):
-    ref = oracle.transfer(prob.src, prob.vals, prob.tgt, prob.degree, weight_kind=weight, lam=lam,
+    ref = oracle.transfer(prob.src, prob.vals, prob.tgt, prob.degree,
+                          weight_kind=CONST if weight == NO_OP else weight, lam=lam,
                           **oracle.problem_kwargs(prob))
     ok = (ref["status"] & 0xF) == 0
     errs = {}

@@ -267,3 +267,22 @@ def test_binding_rejects_bad_shapes_on_grid_operator_and_batch(cpu_as_gpu):
     with pytest.raises(ValueError, match="status must have shape"):
         pcms.Operator(_f64(torch, 100, 2), _f64(torch, 10, 2), 1, rad, 16,
                       status=torch.zeros(9, dtype=torch.uint8))
+
+
+@needs_lib
+def test_workspace_query():
+    """Host-only sizes: the grid holds at least its FP64 and FP32 records and
+    both permutations; the transfer on a grid at least the bucket-ordered
+    field records and the target order; the one-shot call both."""
+    n_src, dim, nf, n_tgt = 1_000_000, 3, 8, 500_000
+    w = pcms.pcms_workspace_query(n_src, dim, nf, n_tgt)
+    assert w["grid_bytes"] >= n_src * (4 * 8 + 3 * 4 + 2 * 4)
+    assert w["transfer_grid_bytes"] >= n_src * nf * 8 + n_tgt * 4
+    assert w["transfer_bytes"] >= w["grid_bytes"] + w["transfer_grid_bytes"]
+    assert w["operator_apply_bytes"] == n_src * nf * 8
+    assert w["noalloc_limit"] == pcms.lib().pcms_noalloc_scratch_bytes() == 128 << 20
+    w2 = pcms.pcms_workspace_query(n_src, dim, nf + 1, n_tgt)   # odd counts pad to even
+    assert w2["operator_apply_bytes"] == n_src * (nf + 2) * 8
+    for bad in ((0, 3, 1, 1), (10, 0, 1, 1), (10, 6, 1, 1), (10, 3, 0, 1), (10, 3, 1, -1)):
+        with pytest.raises(pcms.PcmsError):
+            pcms.pcms_workspace_query(*bad)

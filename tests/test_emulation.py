@@ -53,7 +53,7 @@ def test_emu_dims(dim, degree, mode):
     C.case_dims(BE, dim, degree, mode, scale=0.3)
 
 
-@pytest.mark.parametrize("weight", [1, 2, 3, 4])
+@pytest.mark.parametrize("weight", [1, 2, 3, 4, 5])
 def test_emu_weights(weight):
     C.case_weight(BE, weight)
 

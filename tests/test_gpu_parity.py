@@ -45,7 +45,7 @@ def test_other_dimensions_and_degrees(dim, degree, mode):
 
 
 @pytest.mark.parametrize("weight", [pcms.WEIGHT_C4, pcms.WEIGHT_GAUSSIAN, pcms.WEIGHT_CONST,
-                                    pcms.WEIGHT_IMQ])
+                                    pcms.WEIGHT_IMQ, pcms.WEIGHT_NO_OP])
 def test_weight_variants(weight):
     C.case_weight(BE, weight)
 
@@ -108,3 +108,17 @@ def test_block_sizes_agree():
         got, st2, _ = gpu_transfer(p, pcms.FP64, block=block)
         np.testing.assert_array_equal(st, st2)
         assert np.array_equal(got, base, equal_nan=True)
+
+
+def test_no_op_weight_is_const_on_the_selected_sources():
+    """Table 1's No_Op weight (phi = 1) and Const (phi = 1 inside the radius)
+    give bit-identical transfers: only selected sources enter the fit."""
+    from paper_2510_18838_amd import synth
+    p = synth.uniform_problem(33, 4000, 1500, 3, 2, synth.FIXED, n_fields=2, radius=0.15,
+                              k_cap=64)
+    for prec in (pcms.FP64, pcms.MIXED_REFINE, pcms.MIXED):
+        a, sa, _ = gpu_transfer(p, prec, weight=pcms.WEIGHT_CONST)
+        b, sb, _ = gpu_transfer(p, prec, weight=pcms.WEIGHT_NO_OP)
+        assert np.array_equal(sa, sb)
+        assert np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(a[~np.isnan(a)],
+                                                                            b[~np.isnan(b)])
