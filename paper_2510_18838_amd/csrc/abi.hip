@@ -306,12 +306,12 @@ struct GridLayout {
     size_t o_cs, o_perm, o_iperm, o_spts, o_s32, bytes;
     GridLayout(int64_t n_src, int dim)
     {
-        o_cs = 256;
+        o_cs = align256(sizeof(GridParams));
         o_perm = o_cs + align256(sizeof(int) * ((size_t)cells_cap_for(n_src) + 1));
         o_iperm = o_perm + align256(sizeof(int) * (size_t)n_src);
         o_spts = o_iperm + align256(sizeof(int) * (size_t)n_src);
         o_s32 = o_spts + align256(sizeof(double) * (size_t)n_src * padded_dim(dim));
-        bytes = o_s32 + sizeof(float) * (size_t)n_src * padded_dim32(dim);
+        bytes = o_s32 + sizeof(float) * 2 * (size_t)n_src * dim;   // FP32 + fixed-point
     }
 };
 
@@ -432,10 +432,11 @@ static pcms_status grid_create(int64_t n_src, int32_t dim, const double *inv_sca
         (e = hipMalloc(&g->perm, sizeof(int) * (size_t)n_src)) != hipSuccess ||
         (e = hipMalloc(&g->iperm, sizeof(int) * (size_t)n_src)) != hipSuccess ||
         (e = hipMalloc(&g->spts, sizeof(double) * (size_t)n_src * padded_dim(dim))) != hipSuccess ||
-        (e = hipMalloc(&g->spts32, sizeof(float) * (size_t)n_src * padded_dim32(dim))) != hipSuccess) {
+        (e = hipMalloc(&g->spts32, sizeof(float) * 2 * (size_t)n_src * dim)) != hipSuccess) {
         grid_alloc_free(g);
         return hip_fail(e, "hipMalloc(grid)");
     }
+    g->sq = reinterpret_cast<uint32_t *>(g->spts32 + (size_t)n_src * dim);
     *out = g;
     return PCMS_OK;
 }
@@ -558,6 +559,7 @@ pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, con
     g.iperm = (int *)((char *)sc.p + L.o_iperm);
     g.spts = (double *)((char *)sc.p + L.o_spts);
     g.spts32 = (float *)((char *)sc.p + L.o_s32);
+    g.sq = reinterpret_cast<uint32_t *>(g.spts32 + (size_t)n_src * dim);
     if ((st = build_grid_device(&g, src, cw, ppc, s)) != PCMS_OK) return st;
     return transfer_on_grid(&g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts,
                             s, tgt_vals, status, nullptr);
@@ -639,12 +641,12 @@ pcms_status pcms_operator_build(const double *src, int64_t n_src, int32_t dim, c
     };
     Scratch sc;
     sc.s = s;
-    size_t o_cs = 256;
+    size_t o_cs = (sizeof(GridParams) + 255) & ~(size_t)255;
     size_t o_perm = o_cs + ((sizeof(int) * ((size_t)g.n_cells_cap + 1) + 255) & ~(size_t)255);
     size_t o_iperm = o_perm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
     size_t o_spts = o_iperm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
     size_t o_s32 = o_spts + ((sizeof(double) * (size_t)n_src * padded_dim(dim) + 255) & ~(size_t)255);
-    size_t o_sum = o_s32 + ((sizeof(float) * (size_t)n_src * padded_dim32(dim) + 255) & ~(size_t)255);
+    size_t o_sum = o_s32 + ((sizeof(float) * 2 * (size_t)n_src * dim + 255) & ~(size_t)255);
     if ((st = scratch_alloc(&sc.p, o_sum + 64, s)) != PCMS_OK) return fail(st);
     g.params = (GridParams *)sc.p;
     g.cell_start = (int *)((char *)sc.p + o_cs);
@@ -652,6 +654,7 @@ pcms_status pcms_operator_build(const double *src, int64_t n_src, int32_t dim, c
     g.iperm = (int *)((char *)sc.p + o_iperm);
     g.spts = (double *)((char *)sc.p + o_spts);
     g.spts32 = (float *)((char *)sc.p + o_s32);
+    g.sq = reinterpret_cast<uint32_t *>(g.spts32 + (size_t)n_src * dim);
     int32_t *summary = async ? o.summary : (int32_t *)((char *)sc.p + o_sum);
     if ((st = zero_ints(summary, 4, s)) != PCMS_OK) return fail(st);
     if ((st = build_grid_device(&g, src, cw, ppc, s)) != PCMS_OK) return fail(st);

@@ -204,7 +204,7 @@ __global__ void k_batch_gather_pts(const BatchProb *__restrict__ probs,
                                    const GridParams *__restrict__ params,
                                    const int64_t *__restrict__ pref, int n,
                                    const int *__restrict__ sorted_vals, double *spts, float *spts32,
-                                   int *perm, int *iperm)
+                                   uint32_t *sq, int *perm, int *iperm)
 {
     const int64_t total = pref[n];
     for (int64_t P0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; P0 < total;
@@ -213,9 +213,9 @@ __global__ void k_batch_gather_pts(const BatchProb *__restrict__ probs,
         const BatchProb &B = probs[q];
         const int p = (int)(P0 - B.src_off);
         const int jl = (int)(sorted_vals[P0] - B.src_off);
-        write_records(B.src + (int64_t)jl * B.dim, B.dim, params[q].lo,
+        write_records(B.src + (int64_t)jl * B.dim, B.dim, params[q],
                       spts + B.spts_off + (int64_t)p * padded_dim(B.dim),
-                      spts32 + B.s32_off + (int64_t)p * padded_dim32(B.dim));
+                      spts32 + B.s32_off + (int64_t)p * B.dim, sq + B.s32_off + (int64_t)p * B.dim);
         perm[P0] = jl;
         iperm[B.src_off + jl] = p;
     }
@@ -295,7 +295,7 @@ pcms_status batch_setup(BatchPlan &p)
         tgt += B.n_tgt;
         cs += (int64_t)B.cells_cap + 1;
         sp += (int64_t)B.n_src * padded_dim(B.dim);
-        s32 += (int64_t)B.n_src * padded_dim32(B.dim);
+        s32 += (int64_t)B.n_src * B.dim;
         sv += (int64_t)B.n_src * B.nfs;
         keys += (double)B.cells_cap;
         tkeys += tile_key_bound((double)B.cells_cap, B.dim);
@@ -369,7 +369,7 @@ pcms_status batch_setup(BatchPlan &p)
     const size_t o_tperm = take(sizeof(int) * tgt);
     const size_t o_spts = take(sizeof(double) * sp);
     const size_t o_svals = take(sizeof(double) * sv);
-    const size_t o_s32 = take(sizeof(float) * s32);
+    const size_t o_s32 = take(sizeof(float) * 2 * s32);   // FP32 records, then fixed-point ones
     const size_t o_items = take(sizeof(int4) * std::max<size_t>(sorted.size(), 1));
     const size_t o_ctr = take(sizeof(int) * 4);
     const size_t o_sum = take(sizeof(int32_t) * 4);
@@ -398,6 +398,7 @@ pcms_status batch_setup(BatchPlan &p)
     p.spts = (double *)(w + o_spts);
     p.svals = (double *)(w + o_svals);
     p.spts32 = (float *)(w + o_s32);
+    p.sq = reinterpret_cast<uint32_t *>(p.spts32 + s32);
     p.items = (int4 *)(w + o_items);
     p.counter = (int *)(w + o_ctr);
     p.summary = (int32_t *)(w + o_sum);
@@ -440,6 +441,7 @@ pcms_status batch_setup(BatchPlan &p)
         G.iperm = p.iperm + B.src_off;
         G.spts = p.spts + B.spts_off;
         G.spts32 = p.spts32 + B.s32_off;
+        G.sq = p.sq + B.s32_off;
         G.device = dev;
     }
     return PCMS_OK;
@@ -466,8 +468,8 @@ pcms_status batch_enqueue(BatchPlan &p, hipStream_t s)
                                                               p.k0, p.cs);
     PCMS_HIP(hipGetLastError());
     k_batch_gather_pts<<<grid_for(p.n_src_tot, tpb), tpb, 0, s>>>(p.probs_d, p.params, p.src_pref,
-                                                                 n, p.v0, p.spts, p.spts32, p.perm,
-                                                                 p.iperm);
+                                                                 n, p.v0, p.spts, p.spts32, p.sq,
+                                                                 p.perm, p.iperm);
     PCMS_HIP(hipGetLastError());
     k_batch_scatter_vals<<<grid_for(p.n_src_tot, tpb), tpb, 0, s>>>(p.probs_d, p.src_pref, n,
                                                                    p.iperm, p.svals);
@@ -488,6 +490,7 @@ pcms_status batch_enqueue(BatchPlan &p, hipStream_t s)
         b.cs = p.cs;
         b.spts = p.spts;
         b.spts32 = p.spts32;
+        b.sq = p.sq;
         b.perm = p.perm;
         b.tperm = p.tperm;
         b.svals = p.svals;

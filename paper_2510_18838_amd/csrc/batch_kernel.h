@@ -18,6 +18,7 @@ struct BArgs {
     const int *cs;
     const double *spts;
     const float *spts32;
+    const uint32_t *sq;
     const int *perm;
     const int *tperm;
     const double *svals;
@@ -63,6 +64,7 @@ k_batch_transfer(BArgs b)
         a.cs = b.cs + P.cs_off;
         a.spts = b.spts + P.spts_off;
         a.spts32 = b.spts32 + P.s32_off;
+        a.sq = b.sq + P.s32_off;
         a.perm = b.perm + P.src_off;
         a.tgt = P.tgt;
         a.tperm = b.tperm + P.tgt_off;

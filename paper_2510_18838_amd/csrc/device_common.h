@@ -23,6 +23,10 @@ using std::max;
 using std::min;
 using std::nextafter;
 using std::pow;
+using std::rint;
+using std::log2;
+using std::ldexp;
+using std::ceil;
 using std::sqrt;
 // Called by the emulation build when a lane addresses LDS words outside its own.
 [[noreturn]] void pcms_emu_lds_fault(int e, int words);
@@ -65,6 +69,8 @@ struct GridParams {
     double w[kMaxDim];      // bucket width, raw coordinates
     double inv_w[kMaxDim];  // 1 / w
     double g[kMaxDim];      // metric factors
+    double qs[kMaxDim];     // quantum of the 32-bit source records (a power of two)
+    double iqs[kMaxDim];    // 1 / qs
     double density;         // sources per unit metric volume of the bounding box
 };
 
@@ -95,6 +101,8 @@ PCMS_HD inline void grid_params_compute(const double *lo, const double *hi, int 
         p.w[k] = 1.0;
         p.inv_w[k] = 1.0;
         p.stride[k] = 0;
+        p.qs[k] = 1.0;
+        p.iqs[k] = 1.0;
         ext[k] = 0.0;
     }
     for (int k = 0; k < dim; ++k) {
@@ -105,6 +113,13 @@ PCMS_HD inline void grid_params_compute(const double *lo, const double *hi, int 
             h = 0.0;
         }
         p.lo[k] = l;
+        // quantum 2^(E - 32) with 2^E just above the extent: every source of
+        // the box maps to an integer in [0, 2^32)
+        if (h > l) {
+            const int e = (int)ceil(log2((h - l) * (1.0 + 1.0 / 1048576.0)));
+            p.qs[k] = ldexp(1.0, e - 32);
+            p.iqs[k] = ldexp(1.0, 32 - e);
+        }
         ext[k] = (h - l) * p.g[k];
         if (ext[k] > 0.0) {
             vol *= ext[k];
@@ -234,6 +249,32 @@ PCMS_HD PCMS_INLINE void load_src32(const float *__restrict__ s32, int p, float 
 #pragma unroll
     for (int k = 0; k < D; ++k) s[k] = b[k];
 }
+
+// Sorted sources also keep a 32-bit fixed-point image of their coordinates,
+// q_k = round((s_k - lo_k) / qs_k) with the power-of-two quantum qs_k of
+// their box, packed with no padding (a 3-D point is 12 bytes, one load).  The
+// mixed-precision fit passes read it instead of the FP64 record: it places
+// the source within qs_k / 2 (about 1.2e-10 of the box) of its position, and
+// (q_k - (t_k - lo_k) / qs_k) * qs_k is formed in FP64 without cancellation.
+PCMS_HD PCMS_INLINE uint32_t quantize(double x, double lo, double iqs)
+{
+    const double v = rint((x - lo) * iqs);
+    return (uint32_t)fmin(fmax(v, 0.0), 4294967295.0);
+}
+
+template <int D>
+PCMS_HD PCMS_INLINE void load_srcq(const uint32_t *__restrict__ sq, int p, uint32_t (&q)[D])
+{
+    // adjacent scalar loads, which the compiler merges into one wide load
+    const uint32_t *b = sq + (size_t)p * D;
+#pragma unroll
+    for (int k = 0; k < D; ++k) q[k] = b[k];
+}
+
+// Fused multiply-add in the arithmetic of its operands (__builtin_fma on
+// floats would promote them and compute in FP64).
+PCMS_HD PCMS_INLINE float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+PCMS_HD PCMS_INLINE double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Two consecutive doubles from a 16-byte aligned address, in one load.
 PCMS_HD PCMS_INLINE void load_pair(const double *__restrict__ p, double &x, double &y)

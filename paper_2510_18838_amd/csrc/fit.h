@@ -15,11 +15,12 @@
 //
 // Precision: FP64 assembles G in FP64.  MIXED forms xi_e and w_e in FP32 and
 // accumulates G in FP32; the factorisation, the solve and the evaluation
-// pass are FP64 (FP64 per-neighbour data).  MIXED_REFINE adds FP64 iterative
-// refinement y += G32^{-1}(e_0 - G y) with the residual formed from FP64
-// per-neighbour data, which converges to the FP64 result (one step unless
-// the target is ill-conditioned).  In the mixed modes with lambda = 0 field
-// values are centred on the first kept neighbour's value.
+// pass are FP64 (FP64 per-neighbour data).  MIXED_REFINE assembles its FP32
+// moments from the sources' fixed-point records (one load each) and adds
+// FP64 iterative refinement y += G32^{-1}(e_0 - G y) with the residual formed
+// from FP64 per-neighbour data, which converges to the FP64 result (one step
+// unless the target is ill-conditioned).  In the mixed modes with lambda = 0
+// field values are centred on the first kept neighbour's value.
 #pragma once
 
 #include <type_traits>
@@ -117,7 +118,7 @@ PCMS_HD PCMS_INLINE bool cholesky(T (&A)[M * (M + 1) / 2], T (&inv_diag)[M], dou
     for (int j = 0; j < M; ++j) {
         T s = A[tri<M>(j, j)];
 #pragma unroll
-        for (int k = 0; k < j; ++k) s = __builtin_fma(-A[tri<M>(k, j)], A[tri<M>(k, j)], s);
+        for (int k = 0; k < j; ++k) s = fma_t(-A[tri<M>(k, j)], A[tri<M>(k, j)], s);
         ok = ok && (s > tau);
         T d = sqrt(fmax(s, sizeof(T) == sizeof(double) ? T(1e-300) : T(1e-30)));
         T id = T(1) / d;
@@ -127,7 +128,7 @@ PCMS_HD PCMS_INLINE bool cholesky(T (&A)[M * (M + 1) / 2], T (&inv_diag)[M], dou
         for (int i = j + 1; i < M; ++i) {
             T x = A[tri<M>(j, i)];
 #pragma unroll
-            for (int k = 0; k < j; ++k) x = __builtin_fma(-A[tri<M>(k, j)], A[tri<M>(k, i)], x);
+            for (int k = 0; k < j; ++k) x = fma_t(-A[tri<M>(k, j)], A[tri<M>(k, i)], x);
             A[tri<M>(j, i)] = x * id;
         }
     }
@@ -156,11 +157,34 @@ PCMS_HD PCMS_INLINE void chol_solve(const T (&R)[M * (M + 1) / 2], const T (&inv
     }
 }
 
+// The same solve in T arithmetic throughout (the refinement corrections of
+// MIXED_REFINE, which need only the relative accuracy of the FP32 factor).
+template <int M, typename T>
+PCMS_HD PCMS_INLINE void chol_solve_in(const T (&R)[M * (M + 1) / 2], const T (&inv_diag)[M],
+                                       T (&x)[M])
+{
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        T s = x[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s = fma_t(-R[tri<M>(k, i)], x[k], s);
+        x[i] = s * inv_diag[i];
+    }
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
+        T s = x[i];
+#pragma unroll
+        for (int k = i + 1; k < M; ++k) s = fma_t(-R[tri<M>(i, k)], x[k], s);
+        x[i] = s * inv_diag[i];
+    }
+}
+
 struct KArgs {
     const GridParams *gp;
     const int *cs;
     const double *spts;
-    const float *spts32;   // FP32 records of the sorted sources (mixed precisions)
+    const float *spts32;   // FP32 records of the sorted sources (mixed-precision walks)
+    const uint32_t *sq;    // fixed-point records of the sorted sources (mixed-precision fits)
     const int *perm;
     const double *tgt;
     const int *tperm;
@@ -285,12 +309,50 @@ PCMS_HD PCMS_INLINE int nbr_target(const KArgs &a, const GridParams &gp, int i, 
     return st;
 }
 
-// Loads the coordinates of kept neighbours e0 + j G (j < B) of this lane at
-// once, with their sorted indices; slots past n repeat neighbour 0 and are
-// flagged invalid.
-template <int D, int G, int B, class S_>
-PCMS_HD PCMS_INLINE void load_neighbours(S_ &S, const double *__restrict__ spts, int e0, int n,
-                                         double (&sb)[B][D], bool (&ok)[B], int (&pe)[B])
+// Coordinates of the kept sources in the fit passes.  With Q false they come
+// from the FP64 records and u = (t - s) g is the FP64 offset of the exact
+// predicate; with Q true (the mixed precisions) from the fixed-point records
+// (one load of 4 D bytes instead of two 16-byte ones), u = (tq - q) qs g with
+// tq = (t - lo) / qs formed once per target, which is the offset of the
+// source's fixed-point position lo + q qs, within qs / 2 of its own.
+template <int D, bool UNIT, bool Q>
+struct FitPts {
+    using Rec = typename std::conditional<Q, uint32_t, double>::type;
+    const double *__restrict__ spts;
+    const uint32_t *__restrict__ sq;
+    double t[D];    // the target, or its fixed-point image
+    double sc[D];   // g, or qs g
+
+    PCMS_HD PCMS_INLINE FitPts(const KArgs &a, const GridParams &gp, const double (&tt)[D])
+        : spts(a.spts), sq(a.sq)
+    {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            t[k] = Q ? (tt[k] - gp.lo[k]) * gp.iqs[k] : tt[k];
+            sc[k] = Q ? (UNIT ? gp.qs[k] : gp.qs[k] * gp.g[k]) : gp.g[k];
+        }
+    }
+    PCMS_HD PCMS_INLINE void load(int p, Rec (&r)[D]) const
+    {
+        if constexpr (Q)
+            load_srcq<D>(sq, p, r);
+        else
+            load_src<D>(spts, p, r);
+    }
+    PCMS_HD PCMS_INLINE void offsets(const Rec (&r)[D], double (&u)[D]) const
+    {
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            u[k] = Q ? (t[k] - (double)r[k]) * sc[k] : (UNIT ? t[k] - r[k] : (t[k] - r[k]) * sc[k]);
+    }
+};
+
+// Loads the records of kept neighbours e0 + j G (j < B) of this lane at once,
+// with their sorted indices; slots past n repeat neighbour 0 and are flagged
+// invalid.
+template <int D, int G, int B, class S_, class FP>
+PCMS_HD PCMS_INLINE void load_neighbours(S_ &S, const FP &fp, int e0, int n,
+                                         typename FP::Rec (&sb)[B][D], bool (&ok)[B], int (&pe)[B])
 {
 #pragma unroll
     for (int j = 0; j < B; ++j) {
@@ -299,27 +361,22 @@ PCMS_HD PCMS_INLINE void load_neighbours(S_ &S, const double *__restrict__ spts,
         pe[j] = S.at(ok[j] ? e : 0);
     }
 #pragma unroll
-    for (int j = 0; j < B; ++j) load_src<D>(spts, pe[j], sb[j]);
+    for (int j = 0; j < B; ++j) fp.load(pe[j], sb[j]);
 }
 
-// Per-neighbour local data: monomials p and weight w, in T.
-template <int D, int P, bool UNIT, typename T>
-PCMS_HD PCMS_INLINE void neighbour_data(const GridParams &gp, const double (&t)[D],
-                                        const double *__restrict__ s, double inv_h, double inv_r2,
+// Per-neighbour local data from its offset u = (t - s) g: monomials p of
+// xi = -u / h and the weight w, in T.
+template <int D, int P, typename T>
+PCMS_HD PCMS_INLINE void neighbour_data(const double (&u)[D], double inv_h, double inv_r2,
                                         int weight, T (&p)[Basis<D, P>::M], T &w)
 {
-    double d2;
+    double d2 = u[0] * u[0];
     T xi[D];
-    {
-        double u = UNIT ? (t[0] - s[0]) : (t[0] - s[0]) * gp.g[0];
-        d2 = u * u;
-        xi[0] = (T)(-u * inv_h);
+    xi[0] = (T)(-u[0] * inv_h);
 #pragma unroll
-        for (int k = 1; k < D; ++k) {
-            u = UNIT ? (t[k] - s[k]) : (t[k] - s[k]) * gp.g[k];
-            d2 = __builtin_fma(u, u, d2);
-            xi[k] = (T)(-u * inv_h);
-        }
+    for (int k = 1; k < D; ++k) {
+        d2 = __builtin_fma(u[k], u[k], d2);
+        xi[k] = (T)(-u[k] * inv_h);
     }
     if constexpr (sizeof(T) == sizeof(double)) {
         T q = sqrt((T)(d2 * inv_r2));
@@ -350,20 +407,19 @@ PCMS_HD PCMS_INLINE void field_refs(S_ &S, const KArgs &a, int l0, double (&fref
 // One pass over the n kept sources with the coefficients y: acc[l] = sum_e
 // w_e (p_e . y) (f_{e, l0 + l} - fref[l]), per lane (the caller sums over the
 // group).  B neighbours' loads are issued together.
-template <int D, int P, bool UNIT, int G, int B, class S_>
-PCMS_HD PCMS_INLINE void field_pass(S_ &S, const KArgs &a, const GridParams &gp, int n,
-                                    double inv_h, double inv_r2,
-                                    const double (&y)[Basis<D, P>::M], int l0,
+template <int D, int P, int G, int B, class S_, class FP>
+PCMS_HD PCMS_INLINE void field_pass(S_ &S, const KArgs &a, const FP &fp, int n, double inv_h,
+                                    double inv_r2, const double (&y)[Basis<D, P>::M], int l0,
                                     const double (&fref)[kFieldChunk], double (&acc)[kFieldChunk])
 {
     constexpr int M = Basis<D, P>::M;
 #pragma unroll
     for (int l = 0; l < kFieldChunk; ++l) acc[l] = 0.0;
     for (int e0 = S.g.q; e0 < n; e0 += G * B) {
-        double sb[B][D];
+        typename FP::Rec sb[B][D];
         bool ok[B];
         int pe[B];
-        load_neighbours<D, G, B>(S, a.spts, e0, n, sb, ok, pe);
+        load_neighbours<D, G, B>(S, fp, e0, n, sb, ok, pe);
         double fv[B][kFieldChunk];
 #pragma unroll
         for (int j = 0; j < B; ++j) {
@@ -376,11 +432,12 @@ PCMS_HD PCMS_INLINE void field_pass(S_ &S, const KArgs &a, const GridParams &gp,
         }
 #pragma unroll
         for (int j = 0; j < B; ++j) {
-            double p[M], w;
-            neighbour_data<D, P, UNIT, double>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p, w);
+            double u[D], p[M], w;
+            fp.offsets(sb[j], u);
+            neighbour_data<D, P, double>(u, inv_h, inv_r2, a.weight, p, w);
             double py = 0.0;
 #pragma unroll
-            for (int u = 0; u < M; ++u) py = __builtin_fma(p[u], y[u], py);
+            for (int v = 0; v < M; ++v) py = __builtin_fma(p[v], y[v], py);
             const double N = ok[j] ? w * py : 0.0;
 #pragma unroll
             for (int l = 0; l < kFieldChunk; ++l) acc[l] = __builtin_fma(N, fv[j][l] - fref[l], acc[l]);
@@ -427,7 +484,17 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
     using TA = typename std::conditional<MIXED, float, double>::type;   // assembly type
     // neighbours per lane whose loads are issued together, per pass (fewer
     // where the pass holds more live registers)
-    constexpr int kAsm = MIXED ? 4 : 2, kRef = 1, kApply = 2;
+    constexpr int kAsm = MIXED ? 4 : 2, kRef = MIXED ? 2 : 1, kApply = 2;
+    // The FP32 moments of MIXED_REFINE, which only precondition the
+    // refinement, are assembled from the fixed-point records (one load per
+    // source); every other pass reads the FP64 records, so the weights that
+    // enter the result are those of the exact positions (a weight near the
+    // edge of the support, (1 - q)^4 with 1 - q ~ 1e-7, is too sensitive to
+    // the position for any rounding of it).
+    using FQ = FitPts<D, UNIT, REFINE>;
+    using FP = FitPts<D, UNIT, false>;
+    using RecQ = typename FQ::Rec;
+    using Rec = typename FP::Rec;
     const int ti = a.tperm[i];
     Search<D, UNIT, G> S{gp, a.cs, a.spts, a.spts32, a.perm, {}, L, a.k_cap, a.words, g};
     load_point<D>(a.tgt, ti, S.t);
@@ -440,27 +507,31 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
     if ((st & 0xF) == PCMS_TGT_OK) {
         const double inv_h = 1.0 / sqrt(r2);
         const double inv_r2 = 1.0 / r2;
+        const FP fp(a, gp, S.t);
+        const FQ fq(a, gp, S.t);
         // moment matrix G = sum w p p^T (upper triangle, in TA); lane q takes
         // the neighbours e = q, q + G, ... and the group sums the partials
         TA Gm[MM];
 #pragma unroll
         for (int j = 0; j < MM; ++j) Gm[j] = TA(0);
         for (int e0 = g.q; e0 < n; e0 += G * kAsm) {
-            double sb[kAsm][D];
+            RecQ sb[kAsm][D];
             bool ok[kAsm];
             int pe[kAsm];
-            load_neighbours<D, G, kAsm>(S, a.spts, e0, n, sb, ok, pe);
+            load_neighbours<D, G, kAsm>(S, fq, e0, n, sb, ok, pe);
 #pragma unroll
             for (int j = 0; j < kAsm; ++j) {
+                double uo[D];
+                fq.offsets(sb[j], uo);
                 TA p[M], w;
-                neighbour_data<D, P, UNIT, TA>(gp, S.t, sb[j], inv_h, inv_r2, a.weight, p, w);
+                neighbour_data<D, P, TA>(uo, inv_h, inv_r2, a.weight, p, w);
                 w = ok[j] ? w : TA(0);
 #pragma unroll
                 for (int u = 0; u < M; ++u) {
                     TA wp = w * p[u];
 #pragma unroll
                     for (int v = u; v < M; ++v)
-                        Gm[tri<M>(u, v)] = __builtin_fma(wp, p[v], Gm[tri<M>(u, v)]);
+                        Gm[tri<M>(u, v)] = fma_t(wp, p[v], Gm[tri<M>(u, v)]);
                 }
             }
         }
@@ -482,40 +553,42 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
             // Iterative refinement with an FP32 factor of the FP32 moments as
             // the preconditioner: y += G32^{-1} (e_0 - (G + lambda I) y), the
             // residual formed entirely in FP64 (FP64 weights and monomials),
-            // so y converges to the FP64 solution.  Each step's correction d
-            // predicts the next one as rho |d|, rho the observed contraction
-            // (|d| / |y| for the first step, whose correction is the FP32
-            // solution's error); refinement stops once that prediction is
-            // below 1e-9 |y| (usually after one step), or the correction
-            // itself is below 1e-8 |y|.  Ill-conditioned targets take up to
-            // kMaxRefine steps, and a correction that does not shrink marks
-            // the target singular at FP32 accuracy.
+            // so y converges to the FP64 solution; the correction itself is
+            // solved in FP32, the accuracy of the factor.  Each step's
+            // correction d predicts the next one as rho |d|, rho the observed
+            // contraction (|d| / |y| for the first step, whose correction is
+            // the FP32 solution's error); refinement stops once that
+            // prediction is below 1e-9 |y| (usually after one step), or the
+            // correction itself is below 1e-8 |y|.  Ill-conditioned targets
+            // take up to kMaxRefine steps, and a correction that does not
+            // shrink marks the target singular at FP32 accuracy.
             TA idg[M];
 #pragma unroll
             for (int u = 0; u < M; ++u) Gm[tri<M>(u, u)] += (TA)a.lambda;
             ok = cholesky<M, TA>(Gm, idg, kPivotFloor);
-            chol_solve<M, TA>(Gm, idg, y);
+            {
+                TA y0[M];
+#pragma unroll
+                for (int u = 0; u < M; ++u) y0[u] = u == 0 ? TA(1) : TA(0);
+                chol_solve_in<M, TA>(Gm, idg, y0);
+#pragma unroll
+                for (int u = 0; u < M; ++u) y[u] = (double)y0[u];
+            }
             double nd_prev = 0.0;
             for (int step = 0; ok && step < kMaxRefine; ++step) {
-#ifndef PCMS_HOST_EMULATION
-                // keeps the compiler from hoisting the FP64 conversions of the
-                // factor out of the loop (55 live doubles instead of floats)
-#pragma unroll
-                for (int j = 0; j < MM; ++j) __asm__ volatile("" : "+v"(Gm[j]));
-#endif
                 double res[M];
 #pragma unroll
                 for (int u = 0; u < M; ++u) res[u] = 0.0;
                 for (int e0 = g.q; e0 < n; e0 += G * kRef) {
-                    double sb[kRef][D];
+                    Rec sb[kRef][D];
                     bool okn[kRef];
                     int pe[kRef];
-                    load_neighbours<D, G, kRef>(S, a.spts, e0, n, sb, okn, pe);
+                    load_neighbours<D, G, kRef>(S, fp, e0, n, sb, okn, pe);
 #pragma unroll
                     for (int j = 0; j < kRef; ++j) {
-                        double p[M], w;
-                        neighbour_data<D, P, UNIT, double>(gp, S.t, sb[j], inv_h, inv_r2, a.weight,
-                                                           p, w);
+                        double uo[D], p[M], w;
+                        fp.offsets(sb[j], uo);
+                        neighbour_data<D, P, double>(uo, inv_h, inv_r2, a.weight, p, w);
                         double py = 0.0;
 #pragma unroll
                         for (int u = 0; u < M; ++u) py = __builtin_fma(p[u], y[u], py);
@@ -524,16 +597,17 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                         for (int u = 0; u < M; ++u) res[u] = __builtin_fma(c, p[u], res[u]);
                     }
                 }
+                TA d[M];
 #pragma unroll
                 for (int u = 0; u < M; ++u)
-                    res[u] = g.sum(res[u]) + ((u == 0 ? 1.0 : 0.0) - a.lambda * y[u]);
-                chol_solve<M, TA>(Gm, idg, res);
+                    d[u] = (TA)(g.sum(res[u]) + ((u == 0 ? 1.0 : 0.0) - a.lambda * y[u]));
+                chol_solve_in<M, TA>(Gm, idg, d);
                 double ny = 0.0, nd = 0.0;
 #pragma unroll
                 for (int u = 0; u < M; ++u) {
                     ny = fmax(ny, fabs(y[u]));
-                    nd = fmax(nd, fabs(res[u]));
-                    y[u] += res[u];
+                    nd = fmax(nd, fabs((double)d[u]));
+                    y[u] += (double)d[u];
                 }
                 const double rho = step == 0 ? nd / ny : nd / nd_prev;
                 if (nd <= 1e-8 * ny || rho * nd <= 1e-9 * ny) break;
@@ -548,15 +622,15 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
         if (EMIT) {
             if ((st & 0xF) == PCMS_TGT_OK) {
                 for (int e0 = g.q; e0 < n; e0 += G * kApply) {
-                    double sb[kApply][D];
+                    Rec sb[kApply][D];
                     bool okn[kApply];
                     int pe[kApply];
-                    load_neighbours<D, G, kApply>(S, a.spts, e0, n, sb, okn, pe);
+                    load_neighbours<D, G, kApply>(S, fp, e0, n, sb, okn, pe);
 #pragma unroll
                     for (int j = 0; j < kApply; ++j) {
-                        double p[M], w;
-                        neighbour_data<D, P, UNIT, double>(gp, S.t, sb[j], inv_h, inv_r2, a.weight,
-                                                           p, w);
+                        double uo[D], p[M], w;
+                        fp.offsets(sb[j], uo);
+                        neighbour_data<D, P, double>(uo, inv_h, inv_r2, a.weight, p, w);
                         double py = 0.0;
 #pragma unroll
                         for (int u = 0; u < M; ++u) py = __builtin_fma(p[u], y[u], py);
@@ -572,7 +646,7 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
             for (int l0 = 0; l0 < a.nf; l0 += kFieldChunk) {
                 double acc[kFieldChunk], fref[kFieldChunk];
                 field_refs<MIXED>(S, a, l0, fref);
-                field_pass<D, P, UNIT, G, kApply>(S, a, gp, n, inv_h, inv_r2, y, l0, fref, acc);
+                field_pass<D, P, G, kApply>(S, a, fp, n, inv_h, inv_r2, y, l0, fref, acc);
                 write_fields<G>(a, ti, l0, acc, fref, g);
             }
         }

@@ -353,17 +353,19 @@ __global__ void k_cell_start(const GridParams *__restrict__ gp, const unsigned *
 }
 
 // Sorted coordinates with the padded stride (padding written as zero), their
-// FP32 records fl32(x_k - lo_k), and the inverse permutation.
+// FP32 records fl32(x_k - lo_k) and fixed-point records, and the inverse
+// permutation.
 __global__ void k_gather_pts(const double *__restrict__ src, const int *__restrict__ perm,
-                             const GridParams *__restrict__ gp, int64_t n, int dim,
+                             const GridParams *__restrict__ gpp, int64_t n, int dim,
                              double *__restrict__ spts, float *__restrict__ spts32,
-                             int *__restrict__ iperm)
+                             uint32_t *__restrict__ sq, int *__restrict__ iperm)
 {
     const int dp = padded_dim(dim), dp32 = padded_dim32(dim);
+    const GridParams gp = *gpp;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int64_t j = perm[p];
-        write_records(src + j * dim, dim, gp->lo, spts + p * dp, spts32 + p * dp32);
+        write_records(src + j * dim, dim, gp, spts + p * dp, spts32 + p * dp32, sq + p * dim);
         iperm[j] = (int)p;
     }
 }
@@ -460,7 +462,8 @@ pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
         grid->params, k0, n, grid->cell_start);
     PCMS_HIP(hipGetLastError());
     k_gather_pts<<<grid_blocks(n, 256), 256, 0, s>>>(src, grid->perm, grid->params, n, dim,
-                                                      grid->spts, grid->spts32, grid->iperm);
+                                                      grid->spts, grid->spts32, grid->sq,
+                                                      grid->iperm);
     PCMS_HIP(hipGetLastError());
     scratch_free(raw, s);
     return PCMS_OK;

@@ -23,7 +23,9 @@ struct Grid {
     int *perm;            // device [n_src]: sorted position -> source index
     int *iperm;           // device [n_src]: source index -> sorted position
     double *spts;         // device [n_src * padded_dim(dim)]: sorted coordinates
-    float *spts32;        // device [n_src * dim]: fl32(coordinate - lo), packed
+    float *spts32;        // device [n_src * dim]: fl32(coordinate - lo), packed, followed
+                          // by the fixed-point records sq (one allocation)
+    uint32_t *sq;         // device [n_src * dim]: quantize(coordinate), packed
     int device;
 };
 
@@ -159,7 +161,7 @@ struct BatchProb {
     int64_t tgt_off;      // into the global target order (tperm)
     int64_t cs_off;       // into the global cell_start array
     int64_t spts_off;     // doubles, into the sorted coordinates
-    int64_t s32_off;      // floats, into the sorted FP32 records
+    int64_t s32_off;      // words, into the sorted FP32 and fixed-point records
     int64_t sval_off;     // doubles, into the sorted field records
     unsigned key_off;     // source sort keys: key_off + bucket id
     unsigned tkey_off;    // target sort keys: tkey_off + processing-order key
@@ -188,6 +190,7 @@ struct BatchPlan {
     int *cs = nullptr, *perm = nullptr, *iperm = nullptr, *tperm = nullptr;
     double *spts = nullptr, *svals = nullptr;
     float *spts32 = nullptr;
+    uint32_t *sq = nullptr;
     int4 *items = nullptr;
     int n_items = 0;
     int *counter = nullptr;

@@ -9,12 +9,13 @@
 namespace pcms {
 
 // Writes a source's FP64 record (padded_dim(dim) doubles, the padding zero,
-// with 16-byte stores) and FP32 record (dim floats, fl32(x_k - lo_k)) from its
-// dim coordinates.
+// with 16-byte stores), FP32 record (dim floats, fl32(x_k - lo_k)) and 32-bit
+// fixed-point record (dim words, quantize()) from its dim coordinates.
 __device__ __forceinline__ void write_records(const double *__restrict__ x, int dim,
-                                              const double *__restrict__ lo,
-                                              double *__restrict__ r64, float *__restrict__ r32)
+                                              const GridParams &gp, double *__restrict__ r64,
+                                              float *__restrict__ r32, uint32_t *__restrict__ rq)
 {
+    const double *lo = gp.lo;
     double v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = k < dim ? x[k] : 0.0;
@@ -24,6 +25,9 @@ __device__ __forceinline__ void write_records(const double *__restrict__ x, int 
 #pragma unroll
     for (int k = 0; k < 5; ++k)
         if (k < dim) r32[k] = (float)(v[k] - lo[k]);
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+        if (k < dim) rq[k] = quantize(v[k], lo[k], gp.iqs[k]);
 }
 
 // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous

@@ -82,6 +82,7 @@ KArgs base_args(const LaunchSpec &ls, int block)
     a.cs = ls.grid->cell_start;
     a.spts = ls.grid->spts;
     a.spts32 = ls.grid->spts32;
+    a.sq = ls.grid->sq;
     a.perm = ls.grid->perm;
     a.tgt = ls.tgt;
     a.tperm = ls.tperm;

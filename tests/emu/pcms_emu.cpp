@@ -251,6 +251,11 @@ int main(int argc, char **argv)
     for (int64_t p = 0; p < n_src; ++p)
         for (int q = 0; q < dim; ++q)
             spts32[p * dp32 + q] = (float)(src[(size_t)perm[p] * dim + q] - gp.lo[q]);
+    // fixed-point records as the gather kernel writes them
+    std::vector<uint32_t> sq((size_t)(n_src * dim), 0u);
+    for (int64_t p = 0; p < n_src; ++p)
+        for (int q = 0; q < dim; ++q)
+            sq[p * dim + q] = quantize(src[(size_t)perm[p] * dim + q], gp.lo[q], gp.iqs[q]);
     // targets, in the kernels' processing order
     std::vector<unsigned> tkeys(n_tgt);
     std::vector<int> tperm(n_tgt);
@@ -276,6 +281,7 @@ int main(int argc, char **argv)
     a.cs = cs.data();
     a.spts = spts.data();
     a.spts32 = spts32.data();
+    a.sq = sq.data();
     a.perm = perm.data();
     a.tgt = tgt.data();
     a.tperm = tperm.data();
