@@ -231,7 +231,7 @@ pcms_status pcms_operator_free(pcms_operator *op);
 /* ---------------------------------------------------------------------- */
 /* Batched transfer: many independent problems of uneven size, dimension,  */
 /* degree and field count (each one the operation of pcms_mls_transfer)    */
-/* executed by one persistent kernel from a work queue, with every stage   */
+/* executed from one work queue, largest items first, with every stage     */
 /* captured once into a HIP graph and replayed.                            */
 /* ---------------------------------------------------------------------- */
 
@@ -286,9 +286,11 @@ pcms_status pcms_batch_plan_create(const pcms_problem *problems, int32_t n,
                                    const pcms_batch_opts *opts, pcms_batch_plan **out);
 
 /* Execute the plan on `stream`: every grid build, target ordering and
- * value scatter, then one persistent launch that takes (problem, tile)
- * items from an atomic counter until the queue is empty (problems of
- * dimension 4 or 5 run through the one-problem kernel after it).  The first
+ * value scatter, then the work queue of (problem, tile of targets) items:
+ * one launch per class of problems present (dimension 1-3, degree, metric),
+ * each compiled for its class, with one block per item in decreasing order
+ * of estimated cost (problems of dimension 4 or 5 run through the
+ * one-problem kernel after them).  The first
  * call on a plan with a non-null stream captures the sequence into a HIP
  * graph and later calls replay it (the legacy null stream cannot be
  * captured: there every call enqueues the kernels directly).  summary: DEVICE int32[4] or NULL.  With summary NULL the call waits

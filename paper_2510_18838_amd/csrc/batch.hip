@@ -9,9 +9,12 @@
 // are then contiguous slices of global arrays, laid out exactly as the
 // one-problem path lays out its own grid, so the per-target code (search,
 // moment assembly, solve, evaluation) runs unchanged on every slice.
-// Targets are ordered the same way.  A persistent kernel then takes
-// (problem, tile of targets) work items from an atomic counter -- items were
-// ordered by estimated cost, largest first -- until the queue is empty.
+// Targets are ordered the same way.  The (problem, tile of targets) work
+// items are grouped by the problems' class (dimension, degree, metric) and,
+// within a class, ordered by estimated cost, largest first.  One kernel per
+// class present, each compiled for its class alone (its own register
+// allocation), runs one block per item of its class; blocks are dispatched
+// in queue order, which schedules the largest items first.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -58,8 +61,8 @@ int grid_for(int64_t n, int tpb)
     return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 65536);
 }
 
-// Running min/max keys of every problem, the work counter and the summary.
-__global__ void k_batch_init(long long *bb, int n, int *counter, int32_t *summary)
+// Running min/max keys of every problem and the summary.
+__global__ void k_batch_init(long long *bb, int n, int32_t *summary)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n * kMaxDim) {
@@ -67,10 +70,8 @@ __global__ void k_batch_init(long long *bb, int n, int *counter, int32_t *summar
         bb[(size_t)q * 2 * kMaxDim + k] = LLONG_MAX;
         bb[(size_t)q * 2 * kMaxDim + kMaxDim + k] = LLONG_MIN;
     }
-    if (i == 0) {
-        *counter = 0;
+    if (i == 0)
         for (int k = 0; k < 4; ++k) summary[k] = 0;
-    }
 }
 
 // Per-problem bounding boxes: a block reduces a chunk of the global source
@@ -319,9 +320,10 @@ pcms_status batch_setup(BatchPlan &p)
     p.key_bits = bits_for(keys);
     p.tkey_bits = bits_for(t);
     // work items: tiles of `block` targets of the problems of dimension <= 3,
-    // largest estimated cost first
+    // grouped by class, largest estimated cost first within a class
     std::vector<int4> items;
     std::vector<double> cost;
+    std::vector<int> cls;
     p.outer.clear();
     for (int q = 0; q < n; ++q) {
         const BatchProb &B = p.hp[q];
@@ -335,14 +337,21 @@ pcms_status batch_setup(BatchPlan &p)
             const int c = std::min(p.block, B.n_tgt - t0);
             items.push_back(make_int4(q, t0, c, 0));
             cost.push_back((double)c * (B.k_cap + 16) * (m + 4) * (m + 4));
+            cls.push_back(batch_class(B.dim, B.degree, B.unit));
         }
     }
     std::vector<int> order(items.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return cls[x] != cls[y] ? cls[x] < cls[y] : cost[x] > cost[y];
+    });
     std::vector<int4> sorted(items.size());
     for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
     p.n_items = (int)sorted.size();
+    p.cls_begin.assign(kBatchClasses, 0);
+    p.cls_end.assign(kBatchClasses, 0);
+    for (size_t i = order.size(); i-- > 0;) p.cls_begin[cls[order[i]]] = (int)i;
+    for (size_t i = 0; i < order.size(); ++i) p.cls_end[cls[order[i]]] = (int)i + 1;
     // workspace
     const int64_t nmax = std::max<int64_t>(std::max(src, tgt), 1);
     size_t off = 0;
@@ -371,7 +380,6 @@ pcms_status batch_setup(BatchPlan &p)
     const size_t o_svals = take(sizeof(double) * sv);
     const size_t o_s32 = take(sizeof(float) * 2 * s32);   // FP32 records, then fixed-point ones
     const size_t o_items = take(sizeof(int4) * std::max<size_t>(sorted.size(), 1));
-    const size_t o_ctr = take(sizeof(int) * 4);
     const size_t o_sum = take(sizeof(int32_t) * 4);
     hipError_t e = hipMalloc(&p.ws, off);
     if (e != hipSuccess) {
@@ -400,7 +408,6 @@ pcms_status batch_setup(BatchPlan &p)
     p.spts32 = (float *)(w + o_s32);
     p.sq = reinterpret_cast<uint32_t *>(p.spts32 + s32);
     p.items = (int4 *)(w + o_items);
-    p.counter = (int *)(w + o_ctr);
     p.summary = (int32_t *)(w + o_sum);
     std::vector<int64_t> sp_h(n + 1), tp_h(n + 1), cp_h(n + 1);
     for (int q = 0; q < n; ++q) {
@@ -417,15 +424,8 @@ pcms_status batch_setup(BatchPlan &p)
     PCMS_HIP(hipMemcpy(p.cs_pref, cp_h.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
     if (!sorted.empty())
         PCMS_HIP(hipMemcpy(p.items, sorted.data(), sizeof(int4) * sorted.size(), hipMemcpyHostToDevice));
-    // persistent grid: as many blocks as can be resident at once
-    const size_t shm = (size_t)p.block * p.max_stride * sizeof(int);
-    int per_cu = 0, dev = 0, cus = 0;
+    int dev = 0;
     PCMS_HIP(hipGetDevice(&dev));
-    PCMS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    per_cu = p.precision == PCMS_FP64    ? batch_occupancy<PCMS_FP64>(p.block, shm)
-           : p.precision == PCMS_MIXED   ? batch_occupancy<PCMS_MIXED>(p.block, shm)
-                                         : batch_occupancy<PCMS_MIXED_REFINE>(p.block, shm);
-    p.persist_blocks = std::max(1, std::min(p.n_items, std::max(per_cu, 1) * std::max(cus, 1)));
     // host views of every problem's grid (for the problems of dimension > 3)
     p.views.assign(n, Grid{});
     for (int q = 0; q < n; ++q) {
@@ -451,7 +451,7 @@ pcms_status batch_enqueue(BatchPlan &p, hipStream_t s)
 {
     const int n = p.n;
     const int tpb = 256;
-    k_batch_init<<<grid_for((int64_t)n * kMaxDim, tpb), tpb, 0, s>>>(p.bb, n, p.counter, p.summary);
+    k_batch_init<<<grid_for((int64_t)n * kMaxDim, tpb), tpb, 0, s>>>(p.bb, n, p.summary);
     PCMS_HIP(hipGetLastError());
     k_batch_bbox<<<grid_for((p.n_src_tot + kChunk - 1) / kChunk, 1), 256, 0, s>>>(p.probs_d, p.src_pref, n,
                                                                                  p.bb);
@@ -495,18 +495,20 @@ pcms_status batch_enqueue(BatchPlan &p, hipStream_t s)
         b.tperm = p.tperm;
         b.svals = p.svals;
         b.items = p.items;
-        b.n_items = p.n_items;
-        b.counter = p.counter;
         b.summary = p.summary;
         b.weight = p.weight;
         b.lambda = p.lambda;
         const size_t shm = (size_t)p.block * p.max_stride * sizeof(int);
-        st = p.precision == PCMS_FP64
-               ? batch_launch<PCMS_FP64>(b, p.persist_blocks, p.block, shm, s)
-             : p.precision == PCMS_MIXED
-               ? batch_launch<PCMS_MIXED>(b, p.persist_blocks, p.block, shm, s)
-               : batch_launch<PCMS_MIXED_REFINE>(b, p.persist_blocks, p.block, shm, s);
-        if (st != PCMS_OK) return st;
+        // one launch per class present, in class order
+        for (int c = 0; c < kBatchClasses; ++c) {
+            if (p.cls_end[c] <= p.cls_begin[c]) continue;
+            b.item_begin = p.cls_begin[c];
+            b.item_end = p.cls_end[c];
+            st = p.precision == PCMS_FP64  ? batch_launch<PCMS_FP64>(c, b, p.block, shm, s)
+               : p.precision == PCMS_MIXED ? batch_launch<PCMS_MIXED>(c, b, p.block, shm, s)
+                                           : batch_launch<PCMS_MIXED_REFINE>(c, b, p.block, shm, s);
+            if (st != PCMS_OK) return st;
+        }
     }
     for (int q : p.outer) {
         const BatchProb &B = p.hp[q];

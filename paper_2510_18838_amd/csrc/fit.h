@@ -395,12 +395,12 @@ PCMS_HD PCMS_INLINE void neighbour_data(const double (&u)[D], double inv_h, doub
 // Reference values of fields [l0, l0 + kFieldChunk) for a centred sum: the
 // first kept source's values in the mixed modes (centring leaves the fit
 // unchanged only without regularisation), else zero.
-template <bool MIXED, class S_>
-PCMS_HD PCMS_INLINE void field_refs(S_ &S, const KArgs &a, int l0, double (&fref)[kFieldChunk])
+template <bool MIXED, int FC = kFieldChunk, class S_>
+PCMS_HD PCMS_INLINE void field_refs(S_ &S, const KArgs &a, int l0, double (&fref)[FC])
 {
     const double *sv0 = a.svals + (size_t)S.at(0) * a.nfs;
 #pragma unroll
-    for (int l = 0; l < kFieldChunk; ++l)
+    for (int l = 0; l < FC; ++l)
         fref[l] = (MIXED && a.lambda == 0.0 && l0 + l < a.nf) ? sv0[l0 + l] : 0.0;
 }
 
@@ -445,25 +445,170 @@ PCMS_HD PCMS_INLINE void field_pass(S_ &S, const KArgs &a, const FP &fp, int n, 
     }
 }
 
+// Adds the refinement correction d of step `step` to y and applies the
+// stopping rule: the correction predicts the next one as rho |d|, rho the
+// observed contraction (|d| / |y| for step 0, whose correction is the FP32
+// solution's error).  Returns 0 once that prediction is below 1e-9 |y|, or
+// the correction itself is below 1e-8 |y| (converged); 1 to take another
+// step; 2 when the corrections stop shrinking (at the last step, or above
+// half of |y|) without having reached 1e-5 |y| (singular at FP32 accuracy).
+template <int M, typename TA>
+PCMS_HD PCMS_INLINE int refine_update(double (&y)[M], const TA (&d)[M], int step, double &nd_prev)
+{
+    double ny = 0.0, nd = 0.0;
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+        ny = fmax(ny, fabs(y[u]));
+        nd = fmax(nd, fabs((double)d[u]));
+        y[u] += (double)d[u];
+    }
+    const double rho = step == 0 ? nd / ny : nd / nd_prev;
+    nd_prev = nd;
+    if (nd <= 1e-8 * ny || rho * nd <= 1e-9 * ny) return 0;
+    if (!(nd <= 0.5 * ny) || step == kMaxRefine - 1) return nd <= 1e-5 * ny ? 0 : 2;
+    return 1;
+}
+
+// The correction d = R^{-1} R^{-T} (e_0 - lambda y + res) of a residual
+// partial sum res = -sum_e w_e (p_e . y) p_e (summed over the group here),
+// solved in the arithmetic of the factor.
+template <int M, int G, typename TA>
+PCMS_HD PCMS_INLINE void refine_correction(const TA (&R)[M * (M + 1) / 2], const TA (&idg)[M],
+                                           const double (&y)[M], const double (&res)[M],
+                                           double lambda, Grp<G> g, TA (&d)[M])
+{
+#pragma unroll
+    for (int u = 0; u < M; ++u) d[u] = (TA)(g.sum(res[u]) + ((u == 0 ? 1.0 : 0.0) - lambda * y[u]));
+    chol_solve_in<M, TA>(R, idg, d);
+}
+
+// Refinement steps step0, step0 + 1, ... of y = (G + lambda I)^{-1} e_0 with
+// the factor R of the FP32 moments as preconditioner: each step is one pass
+// over the n kept sources forming the residual from FP64 data, then
+// refine_update.  nd_prev: the previous correction's size.  Returns false
+// when the target is singular at FP32 accuracy.
+template <int D, int P, int G, int K, class S_, class FP, typename TA>
+PCMS_HD PCMS_INLINE bool refine_steps(S_ &S, const KArgs &a, const FP &fp, int n, double inv_h,
+                                      double inv_r2, const TA (&R)[Basis<D, P>::MM],
+                                      const TA (&idg)[Basis<D, P>::M], double (&y)[Basis<D, P>::M],
+                                      int step0, double nd_prev)
+{
+    constexpr int M = Basis<D, P>::M;
+    for (int step = step0; step < kMaxRefine; ++step) {
+        double res[M];
+#pragma unroll
+        for (int u = 0; u < M; ++u) res[u] = 0.0;
+        for (int e0 = S.g.q; e0 < n; e0 += G * K) {
+            typename FP::Rec sb[K][D];
+            bool okn[K];
+            int pe[K];
+            load_neighbours<D, G, K>(S, fp, e0, n, sb, okn, pe);
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                double uo[D], p[M], w;
+                fp.offsets(sb[j], uo);
+                neighbour_data<D, P, double>(uo, inv_h, inv_r2, a.weight, p, w);
+                double py = 0.0;
+#pragma unroll
+                for (int u = 0; u < M; ++u) py = __builtin_fma(p[u], y[u], py);
+                const double c = okn[j] ? -w * py : 0.0;
+#pragma unroll
+                for (int u = 0; u < M; ++u) res[u] = __builtin_fma(c, p[u], res[u]);
+            }
+        }
+        TA d[M];
+        refine_correction<M, G, TA>(R, idg, y, res, a.lambda, S.g, d);
+        const int r = refine_update<M, TA>(y, d, step, nd_prev);
+        if (r == 0) return true;
+        if (r == 2) return false;
+    }
+    return true;
+}
+
+// field_pass with the first refinement step folded in: besides the field
+// sums acc with the coefficients y, the same pass forms the residual partial
+// sum res = -sum_e w_e (p_e . y) p_e and, in FP32, the moments of the
+// centred fields Bm[u][l] = sum_e w_e p_e,u (f_{e, l0 + l} - fref[l]).  The
+// correction d of the residual then moves every fitted value by d . Bm[.][l]
+// (the fit is linear in y), which needs no further pass; Bm only has to be
+// accurate relative to that correction.
+template <int D, int P, int G, int B, int FC, class S_, class FP>
+PCMS_HD PCMS_INLINE void field_pass_fused(S_ &S, const KArgs &a, const FP &fp, int n, double inv_h,
+                                          double inv_r2, const double (&y)[Basis<D, P>::M], int l0,
+                                          const double (&fref)[FC], double (&acc)[FC],
+                                          double (&res)[Basis<D, P>::M],
+                                          float (&Bm)[Basis<D, P>::M][FC])
+{
+    constexpr int M = Basis<D, P>::M;
+#pragma unroll
+    for (int l = 0; l < FC; ++l) acc[l] = 0.0;
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+        res[u] = 0.0;
+#pragma unroll
+        for (int l = 0; l < FC; ++l) Bm[u][l] = 0.0f;
+    }
+    for (int e0 = S.g.q; e0 < n; e0 += G * B) {
+        typename FP::Rec sb[B][D];
+        bool ok[B];
+        int pe[B];
+        load_neighbours<D, G, B>(S, fp, e0, n, sb, ok, pe);
+        double fv[B][FC];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const double *sv = a.svals + (size_t)pe[j] * a.nfs + l0;
+#pragma unroll
+            for (int h = 0; h < FC / 2; ++h) {
+                fv[j][2 * h] = fv[j][2 * h + 1] = 0.0;
+                if (l0 + 2 * h < a.nfs) load_pair(sv + 2 * h, fv[j][2 * h], fv[j][2 * h + 1]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            double u[D], p[M], w;
+            fp.offsets(sb[j], u);
+            neighbour_data<D, P, double>(u, inv_h, inv_r2, a.weight, p, w);
+            w = ok[j] ? w : 0.0;
+            double py = 0.0;
+#pragma unroll
+            for (int v = 0; v < M; ++v) py = __builtin_fma(p[v], y[v], py);
+            const double N = w * py;
+            float wf[FC];
+#pragma unroll
+            for (int l = 0; l < FC; ++l) {
+                const double df = fv[j][l] - fref[l];
+                acc[l] = __builtin_fma(N, df, acc[l]);
+                wf[l] = (float)(w * df);
+            }
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                res[v] = __builtin_fma(-N, p[v], res[v]);
+                const float pv = (float)p[v];
+#pragma unroll
+                for (int l = 0; l < FC; ++l) Bm[v][l] = fma_t(pv, wf[l], Bm[v][l]);
+            }
+        }
+    }
+}
+
 // Group sums of a field chunk, written to the target's outputs (or to its
 // staged record, whose padding past nf receives zeros).
-template <int G>
-PCMS_HD PCMS_INLINE void write_fields(const KArgs &a, int ti, int l0,
-                                      const double (&acc)[kFieldChunk],
-                                      const double (&fref)[kFieldChunk], Grp<G> g)
+template <int G, int FC = kFieldChunk>
+PCMS_HD PCMS_INLINE void write_fields(const KArgs &a, int ti, int l0, const double (&acc)[FC],
+                                      const double (&fref)[FC], Grp<G> g)
 {
-    double v[kFieldChunk];
+    double v[FC];
 #pragma unroll
-    for (int l = 0; l < kFieldChunk; ++l) v[l] = g.sum(acc[l]) + fref[l];
+    for (int l = 0; l < FC; ++l) v[l] = g.sum(acc[l]) + fref[l];
     if (a.stage) {
         double *rec = a.stage + (size_t)ti * a.nfs + l0;
 #pragma unroll
-        for (int h = 0; h < kFieldChunk / 2; ++h)
+        for (int h = 0; h < FC / 2; ++h)
             if (l0 + 2 * h < a.nfs && (h % G) == g.q) store_pair(rec + 2 * h, v[2 * h], v[2 * h + 1]);
         return;
     }
 #pragma unroll
-    for (int l = 0; l < kFieldChunk; ++l)
+    for (int l = 0; l < FC; ++l)
         if (l0 + l < a.nf && (l % G) == g.q) a.out[(size_t)(l0 + l) * a.n_tgt + ti] = v[l];
 }
 
@@ -494,14 +639,20 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
     using FQ = FitPts<D, UNIT, REFINE>;
     using FP = FitPts<D, UNIT, false>;
     using RecQ = typename FQ::Rec;
+    // small bases: the first refinement step of MIXED_REFINE rides on the
+    // evaluation pass (its FP32 field moments fit in registers)
+    // (the first kFused fields; their FP32 field moments fit in registers)
+    constexpr int kFused = 4;
+    constexpr bool FUSED = REFINE && !EMIT && M <= 6;
     using Rec = typename FP::Rec;
     const int ti = a.tperm[i];
     Search<D, UNIT, G> S{gp, a.cs, a.spts, a.spts32, a.perm, {}, L, a.k_cap, a.words, g};
     load_point<D>(a.tgt, ti, S.t);
     int n_found, n;
     double r2;
-    // FP32 walks where a point's FP32 record is one load (at most 16 bytes)
-    int st = select_target<D, UNIT, G, MIXED && D <= 4>(S, a, n_found, n, r2);
+    // FP32 walks where they save loads: a point's FP32 record is one load (at
+    // most 16 bytes) and its FP64 record is two (3-D and 4-D)
+    int st = select_target<D, UNIT, G, MIXED && D >= 3 && D <= 4>(S, a, n_found, n, r2);
     if ((st & 0xF) == PCMS_TGT_OK && n < M) st |= PCMS_TGT_UNDERDETERMINED;
     double y[M];
     if ((st & 0xF) == PCMS_TGT_OK) {
@@ -538,17 +689,18 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
 #pragma unroll
         for (int j = 0; j < MM; ++j) Gm[j] = g.sum(Gm[j]);
         bool ok;
+        TA idg[M];   // inverse diagonal of the FP32 factor (MIXED_REFINE)
 #pragma unroll
         for (int u = 0; u < M; ++u) y[u] = u == 0 ? 1.0 : 0.0;
         if (!REFINE) {
             // FP64 factor of G + lambda I and the solve y = G^{-1} e_0
-            double R[MM], idg[M];
+            double R[MM], idd[M];
 #pragma unroll
             for (int j = 0; j < MM; ++j) R[j] = (double)Gm[j];
 #pragma unroll
             for (int u = 0; u < M; ++u) R[tri<M>(u, u)] += a.lambda;
-            ok = cholesky<M, double>(R, idg, MIXED ? kPivotFloorF32 : kPivotFloor);
-            chol_solve<M, double>(R, idg, y);
+            ok = cholesky<M, double>(R, idd, MIXED ? kPivotFloorF32 : kPivotFloor);
+            chol_solve<M, double>(R, idd, y);
         } else {
             // Iterative refinement with an FP32 factor of the FP32 moments as
             // the preconditioner: y += G32^{-1} (e_0 - (G + lambda I) y), the
@@ -562,7 +714,6 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
             // correction itself is below 1e-8 |y|.  Ill-conditioned targets
             // take up to kMaxRefine steps, and a correction that does not
             // shrink marks the target singular at FP32 accuracy.
-            TA idg[M];
 #pragma unroll
             for (int u = 0; u < M; ++u) Gm[tri<M>(u, u)] += (TA)a.lambda;
             ok = cholesky<M, TA>(Gm, idg, kPivotFloor);
@@ -574,49 +725,9 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
 #pragma unroll
                 for (int u = 0; u < M; ++u) y[u] = (double)y0[u];
             }
-            double nd_prev = 0.0;
-            for (int step = 0; ok && step < kMaxRefine; ++step) {
-                double res[M];
-#pragma unroll
-                for (int u = 0; u < M; ++u) res[u] = 0.0;
-                for (int e0 = g.q; e0 < n; e0 += G * kRef) {
-                    Rec sb[kRef][D];
-                    bool okn[kRef];
-                    int pe[kRef];
-                    load_neighbours<D, G, kRef>(S, fp, e0, n, sb, okn, pe);
-#pragma unroll
-                    for (int j = 0; j < kRef; ++j) {
-                        double uo[D], p[M], w;
-                        fp.offsets(sb[j], uo);
-                        neighbour_data<D, P, double>(uo, inv_h, inv_r2, a.weight, p, w);
-                        double py = 0.0;
-#pragma unroll
-                        for (int u = 0; u < M; ++u) py = __builtin_fma(p[u], y[u], py);
-                        const double c = okn[j] ? -w * py : 0.0;
-#pragma unroll
-                        for (int u = 0; u < M; ++u) res[u] = __builtin_fma(c, p[u], res[u]);
-                    }
-                }
-                TA d[M];
-#pragma unroll
-                for (int u = 0; u < M; ++u)
-                    d[u] = (TA)(g.sum(res[u]) + ((u == 0 ? 1.0 : 0.0) - a.lambda * y[u]));
-                chol_solve_in<M, TA>(Gm, idg, d);
-                double ny = 0.0, nd = 0.0;
-#pragma unroll
-                for (int u = 0; u < M; ++u) {
-                    ny = fmax(ny, fabs(y[u]));
-                    nd = fmax(nd, fabs((double)d[u]));
-                    y[u] += (double)d[u];
-                }
-                const double rho = step == 0 ? nd / ny : nd / nd_prev;
-                if (nd <= 1e-8 * ny || rho * nd <= 1e-9 * ny) break;
-                if (!(nd <= 0.5 * ny) || step == kMaxRefine - 1) {
-                    if (!(nd <= 1e-5 * ny)) ok = false;
-                    break;
-                }
-                nd_prev = nd;
-            }
+            // with FUSED the first step is taken inside the evaluation pass
+            if (!FUSED && ok)
+                ok = refine_steps<D, P, G, kRef>(S, a, fp, n, inv_h, inv_r2, Gm, idg, y, 0, 0.0);
         }
         if (!ok) st |= PCMS_TGT_SINGULAR;
         if (EMIT) {
@@ -643,7 +754,38 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
                 }
             }
         } else if ((st & 0xF) == PCMS_TGT_OK) {
-            for (int l0 = 0; l0 < a.nf; l0 += kFieldChunk) {
+            int l_begin = 0;
+            if constexpr (FUSED) {
+                // the first chunk of fields with the first refinement step:
+                // when one step is enough, the chunk's values are those of
+                // the refined y; otherwise refinement continues with passes
+                // of its own and the chunk is evaluated again
+                double acc[kFused], fref[kFused], res[M];
+                float Bm[M][kFused];
+                field_refs<MIXED, kFused>(S, a, 0, fref);
+                field_pass_fused<D, P, G, 1, kFused>(S, a, fp, n, inv_h, inv_r2, y, 0, fref, acc,
+                                                     res, Bm);
+                TA d[M];
+                refine_correction<M, G, TA>(Gm, idg, y, res, a.lambda, g, d);
+                double nd = 0.0;
+                const int r = refine_update<M, TA>(y, d, 0, nd);
+                if (r == 0) {
+#pragma unroll
+                    for (int l = 0; l < kFused; ++l) {
+                        double c = 0.0;
+#pragma unroll
+                        for (int u = 0; u < M; ++u) c = __builtin_fma((double)d[u], (double)Bm[u][l], c);
+                        acc[l] += c;
+                    }
+                    write_fields<G, kFused>(a, ti, 0, acc, fref, g);
+                    l_begin = kFused;
+                } else if (r == 2 ||
+                           !refine_steps<D, P, G, kRef>(S, a, fp, n, inv_h, inv_r2, Gm, idg, y, 1, nd)) {
+                    st |= PCMS_TGT_SINGULAR;
+                    l_begin = a.nf;
+                }
+            }
+            for (int l0 = l_begin; l0 < a.nf; l0 += kFieldChunk) {
                 double acc[kFieldChunk], fref[kFieldChunk];
                 field_refs<MIXED>(S, a, l0, fref);
                 field_pass<D, P, G, kApply>(S, a, fp, n, inv_h, inv_r2, y, l0, fref, acc);

@@ -193,9 +193,10 @@ struct BatchPlan {
     uint32_t *sq = nullptr;
     int4 *items = nullptr;
     int n_items = 0;
-    int *counter = nullptr;
+    // per class of problems: its slice [cls_begin, cls_end) of the queue
+    std::vector<int> cls_begin, cls_end;
     int32_t *summary = nullptr;       // device [4]
-    int persist_blocks = 0;
+
     std::vector<int> outer;           // problems of dimension > 3: one-problem kernel
     std::vector<Grid> views;          // host views of every problem's grid slices
     hipGraph_t graph = nullptr;
