@@ -214,9 +214,9 @@ __global__ void k_batch_gather_pts(const BatchProb *__restrict__ probs,
         const BatchProb &B = probs[q];
         const int p = (int)(P0 - B.src_off);
         const int jl = (int)(sorted_vals[P0] - B.src_off);
-        write_records(B.src + (int64_t)jl * B.dim, B.dim, params[q],
-                      spts + B.spts_off + (int64_t)p * padded_dim(B.dim),
-                      spts32 + B.s32_off + (int64_t)p * B.dim, sq + B.s32_off + (int64_t)p * B.dim);
+        write_records_dim(B.src + (int64_t)jl * B.dim, B.dim, params[q],
+                          spts + B.spts_off + (int64_t)p * padded_dim(B.dim),
+                          spts32 + B.s32_off + (int64_t)p * B.dim, sq + B.s32_off + (int64_t)p * B.dim);
         perm[P0] = jl;
         iperm[B.src_off + jl] = p;
     }
@@ -234,8 +234,12 @@ __global__ void k_batch_scatter_vals(const BatchProb *__restrict__ probs,
         const BatchProb &B = probs[q];
         const int64_t jl = j - B.src_off;
         double *row = svals + B.sval_off + (int64_t)iperm[j] * B.nfs;
-        for (int l = 0; l < B.nf; ++l) row[l] = B.vals[(int64_t)l * B.n_src + jl];
-        if (B.nfs > B.nf) row[B.nf] = 0.0;
+        // whole 16-byte words (the records are 16-byte aligned)
+        for (int l = 0; l < B.nfs; l += 2) {
+            const double a = B.vals[(int64_t)l * B.n_src + jl];
+            const double b = l + 1 < B.nf ? B.vals[(int64_t)(l + 1) * B.n_src + jl] : 0.0;
+            *reinterpret_cast<double2 *>(row + l) = make_double2(a, b);
+        }
     }
 }
 

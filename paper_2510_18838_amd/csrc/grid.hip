@@ -355,17 +355,18 @@ __global__ void k_cell_start(const GridParams *__restrict__ gp, const unsigned *
 // Sorted coordinates with the padded stride (padding written as zero), their
 // FP32 records fl32(x_k - lo_k) and fixed-point records, and the inverse
 // permutation.
+template <int D>
 __global__ void k_gather_pts(const double *__restrict__ src, const int *__restrict__ perm,
-                             const GridParams *__restrict__ gpp, int64_t n, int dim,
+                             const GridParams *__restrict__ gpp, int64_t n,
                              double *__restrict__ spts, float *__restrict__ spts32,
                              uint32_t *__restrict__ sq, int *__restrict__ iperm)
 {
-    const int dp = padded_dim(dim), dp32 = padded_dim32(dim);
+    constexpr int DP = padded_dim(D);
     const GridParams gp = *gpp;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int64_t j = perm[p];
-        write_records(src + j * dim, dim, gp, spts + p * dp, spts32 + p * dp32, sq + p * dim);
+        write_records<D>(src + j * D, gp, spts + p * DP, spts32 + p * D, sq + p * D);
         iperm[j] = (int)p;
     }
 }
@@ -373,7 +374,9 @@ __global__ void k_gather_pts(const double *__restrict__ src, const int *__restri
 // Fields into bucket order, [n][nf]: read each field coalesced in source
 // order, write the whole row of a source at its sorted slot.
 // Field values of source j to its sorted slot as one record of padded_dim(nf)
-// doubles (the padding written as zero).
+// doubles (the padding written as zero): each field is read coalesced in
+// source order, and the record is written in whole 16-byte words (a scattered
+// 8-byte store per field left the record's line to be merged in pieces).
 __global__ void k_scatter_vals(const double *__restrict__ vals, const int *__restrict__ iperm,
                                int64_t n, int nf, double *__restrict__ svals)
 {
@@ -381,8 +384,20 @@ __global__ void k_scatter_vals(const double *__restrict__ vals, const int *__res
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * blockDim.x) {
         double *row = svals + (int64_t)iperm[j] * nfs;
-        for (int l = 0; l < nf; ++l) row[l] = vals[(int64_t)l * n + j];
-        if (nfs > nf) row[nf] = 0.0;
+        int l = 0;
+        for (; l + 8 <= nf; l += 8) {
+            double v[8];
+#pragma unroll
+            for (int h = 0; h < 8; ++h) v[h] = vals[(int64_t)(l + h) * n + j];
+#pragma unroll
+            for (int h = 0; h < 8; h += 2)
+                *reinterpret_cast<double2 *>(row + l + h) = make_double2(v[h], v[h + 1]);
+        }
+        for (; l < nfs; l += 2) {
+            const double a = vals[(int64_t)l * n + j];
+            const double b = l + 1 < nf ? vals[(int64_t)(l + 1) * n + j] : 0.0;
+            *reinterpret_cast<double2 *>(row + l) = make_double2(a, b);
+        }
     }
 }
 
@@ -461,9 +476,18 @@ pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
     k_cell_start<<<grid_blocks((int64_t)grid->n_cells_cap + 1, 256), 256, 0, s>>>(
         grid->params, k0, n, grid->cell_start);
     PCMS_HIP(hipGetLastError());
-    k_gather_pts<<<grid_blocks(n, 256), 256, 0, s>>>(src, grid->perm, grid->params, n, dim,
-                                                      grid->spts, grid->spts32, grid->sq,
-                                                      grid->iperm);
+    {
+        const int blocks = grid_blocks(n, 256);
+        switch (dim) {
+#define PCMS_GATHER(DD)                                                                        \
+    case DD:                                                                                   \
+        k_gather_pts<DD><<<blocks, 256, 0, s>>>(src, grid->perm, grid->params, n, grid->spts,  \
+                                                grid->spts32, grid->sq, grid->iperm);          \
+        break;
+            PCMS_GATHER(1) PCMS_GATHER(2) PCMS_GATHER(3) PCMS_GATHER(4) PCMS_GATHER(5)
+#undef PCMS_GATHER
+        }
+    }
     PCMS_HIP(hipGetLastError());
     scratch_free(raw, s);
     return PCMS_OK;

@@ -8,26 +8,38 @@
 
 namespace pcms {
 
-// Writes a source's FP64 record (padded_dim(dim) doubles, the padding zero,
-// with 16-byte stores), FP32 record (dim floats, fl32(x_k - lo_k)) and 32-bit
-// fixed-point record (dim words, quantize()) from its dim coordinates.
-__device__ __forceinline__ void write_records(const double *__restrict__ x, int dim,
-                                              const GridParams &gp, double *__restrict__ r64,
-                                              float *__restrict__ r32, uint32_t *__restrict__ rq)
+// Writes a source's FP64 record (padded_dim(D) doubles, the padding zero,
+// with 16-byte stores), FP32 record (D floats, fl32(x_k - lo_k)) and 32-bit
+// fixed-point record (D words, quantize()) from its D coordinates.
+template <int D>
+__device__ __forceinline__ void write_records(const double *__restrict__ x, const GridParams &gp,
+                                              double *__restrict__ r64, float *__restrict__ r32,
+                                              uint32_t *__restrict__ rq)
 {
-    const double *lo = gp.lo;
-    double v[8];
+    constexpr int DP = padded_dim(D);
+    double v[DP];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = k < dim ? x[k] : 0.0;
+    for (int k = 0; k < DP; ++k) v[k] = k < D ? x[k] : 0.0;
 #pragma unroll
-    for (int k = 0; k < 6; k += 2)
-        if (k < dim) *reinterpret_cast<double2 *>(r64 + k) = make_double2(v[k], v[k + 1]);
+    for (int k = 0; k < DP; k += 2) *reinterpret_cast<double2 *>(r64 + k) = make_double2(v[k], v[k + 1]);
 #pragma unroll
-    for (int k = 0; k < 5; ++k)
-        if (k < dim) r32[k] = (float)(v[k] - lo[k]);
+    for (int k = 0; k < D; ++k) r32[k] = (float)(v[k] - gp.lo[k]);
 #pragma unroll
-    for (int k = 0; k < 5; ++k)
-        if (k < dim) rq[k] = quantize(v[k], lo[k], gp.iqs[k]);
+    for (int k = 0; k < D; ++k) rq[k] = quantize(v[k], gp.lo[k], gp.iqs[k]);
+}
+
+// The same for a dimension known at run time.
+__device__ __forceinline__ void write_records_dim(const double *__restrict__ x, int dim,
+                                                  const GridParams &gp, double *__restrict__ r64,
+                                                  float *__restrict__ r32, uint32_t *__restrict__ rq)
+{
+    switch (dim) {
+    case 1: write_records<1>(x, gp, r64, r32, rq); break;
+    case 2: write_records<2>(x, gp, r64, r32, rq); break;
+    case 3: write_records<3>(x, gp, r64, r32, rq); break;
+    case 4: write_records<4>(x, gp, r64, r32, rq); break;
+    default: write_records<5>(x, gp, r64, r32, rq); break;
+    }
 }
 
 // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
