@@ -88,13 +88,15 @@ def roofline(name, n_tgt, kernel_ms, traffic=None, kernel="k_transfer"):
 
 
 def time_transfer(torch, pcms, p, src, vals, tgt, rad, precision, steps, warmup, out, st,
-                  summary):
+                  summary, lbvh=False):
     """K one-shot transfers enqueued back to back (PCMS_ASYNC, statuses into a
     device summary), bracketed by device synchronisations: ms per step from
     the host clock over the K steps, each step's duration from HIP events
     recorded on the launch stream (median, min), and the phases' HIP-event
-    times inside the library (PCMS_PROFILE, averaged over the K steps)."""
-    o = pcms.opts(precision=precision, flags=pcms.PROFILE | pcms.ASYNC, summary=summary)
+    times inside the library (PCMS_PROFILE, averaged over the K steps).
+    lbvh: each step builds an LBVH instead of the uniform grid."""
+    flags = pcms.PROFILE | pcms.ASYNC | (pcms.LBVH if lbvh else 0)
+    o = pcms.opts(precision=precision, flags=flags, summary=summary)
 
     def call():
         pcms.pcms_mls_transfer(src, vals, tgt, p.degree, rad, p.k_cap, inv_scale=p.inv_scale,
@@ -117,6 +119,36 @@ def time_transfer(torch, pcms, p, src, vals, tgt, rad, precision, steps, warmup,
     phases = {k: v / max(calls, 1) for k, v in sums.items()}
     return {"ms_per_step": ms, "ms_median": float(np.median(per)), "ms_min": float(per[0]),
             "phases_ms": phases}
+
+
+def lbvh_leg(torch, pcms, p, name, src, vals, tgt, rad, precision, label, steps, summary,
+             grid_row, grid_out):
+    """The same one-shot transfer on the LBVH search backend: timing, phases
+    and roofline like the grid's, the speed ratio to the grid, and the
+    agreement with the grid's outputs (statuses identical, values to
+    rounding)."""
+    m = tgt.shape[0]
+    out = torch.empty((p.n_fields, m), dtype=torch.float64, device=tgt.device)
+    st = torch.empty(m, dtype=torch.uint8, device=tgt.device)
+    t = time_transfer(torch, pcms, p, src, vals, tgt, rad, precision, steps, 2, out, st, summary,
+                      lbvh=True)
+    t["value"] = m / (t["ms_per_step"] * 1e-3)
+    t["roofline"] = roofline(name, m, t["phases_ms"]["search_fit"],
+                             load_traffic(f"{name}_lbvh_{label}", source_digest()))
+    t["speedup_vs_grid"] = grid_row["ms_per_step"] / t["ms_per_step"]
+    g_out, g_st = grid_out
+    b_out, b_st = out.cpu().numpy(), st.cpu().numpy()
+    t["statuses_equal_grid"] = bool(np.array_equal(g_st, b_st))
+    ok = ((g_st & 0xF) == 0) & (g_st == b_st)
+    diff = 0.0
+    for l in range(p.n_fields):
+        ref = g_out[l][ok]
+        if ref.size:
+            diff = max(diff, float(np.abs(b_out[l][ok] - ref).max() / np.abs(ref).max()))
+    t["max_rel_diff_vs_grid"] = diff
+    log(f"{name} {label} on the LBVH: {t['ms_per_step']:.3f} ms/step "
+        f"({t['speedup_vs_grid']:.2f}x the grid), phases {t['phases_ms']}")
+    return t
 
 
 def oracle_error(orc, p, out, st, n_sample, seed):
@@ -362,14 +394,15 @@ def batched_leg(torch, pcms, synth, dev, steps, orc=None):
     }
 
 
-def configs_leg(torch, pcms, synth, dev, steps, orc=None):
+def configs_leg(torch, pcms, synth, dev, steps, orc=None, lbvh=True):
     """The other single-GPU workloads: the 2-D lattice transfer (1M -> 1M,
     quadratic, fixed radius 3.5 cells, 4 fields), the 5-D transfer (2M -> 2M,
     linear, growing radius in a standardising metric, 4 fields) and the small
     2-D correctness case (2k -> 1.5k, linear, fixed radius): one-shot steps in
     FP64 and MIXED_REFINE timed like the headline, each precision's roofline
     from its search-and-fit kernel's event time, the mixed path's error
-    against FP64 (all targets) and both against the oracle on a sample."""
+    against FP64 (all targets) and both against the oracle on a sample.  The
+    5-D transfer is also timed on the LBVH search backend."""
     rows = {}
     digest = source_digest()
     summary = torch.zeros(4, dtype=torch.int32, device=dev)
@@ -402,6 +435,11 @@ def configs_leg(torch, pcms, synth, dev, steps, orc=None):
         row["mixed_refine_max_rel_err_vs_fp64"] = err
         row["mixed_speedup"] = row["fp64"]["ms_per_step"] / row["mixed_refine"]["ms_per_step"]
         row["valid_targets"] = int(ok.sum())
+        if name == "c5" and lbvh:
+            row["lbvh"] = {label: lbvh_leg(torch, pcms, p, name, src, vals, tgt, rad, prec, label,
+                                           steps, summary, row[label], outs[label])
+                           for label, prec in (("fp64", pcms.FP64),
+                                               ("mixed_refine", pcms.MIXED_REFINE))}
         if orc is not None:
             for label in ("fp64", "mixed_refine"):
                 e, n_ok = oracle_error(orc, p, *outs[label], n_sample=2000, seed=7)
@@ -430,6 +468,8 @@ def main():
                     help="skip the batched leg (512 uneven problems in one persistent launch)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other single-GPU workloads (2-D lattice, 5-D, small 2-D)")
+    ap.add_argument("--no-lbvh", action="store_true",
+                    help="skip the LBVH search-backend legs")
     ap.add_argument("--roundtrip", action="store_true",
                     help="only run the round-trip accuracy experiment (source -> target -> "
                          "source iterations of the Eq. 4 field) and print its table as JSON")
@@ -535,6 +575,10 @@ def main():
         result["accuracy"] = {"max_rel_err_vs_fp64_all_targets": err}
         log(f"fp64 {ms64:.3f} ms/step; headline vs fp64 max rel err {err:.3e}")
 
+    if not args.no_lbvh:
+        result["lbvh"] = lbvh_leg(torch, pcms, p, "c3", src, vals, tgt, rad, prec, args.precision,
+                                  args.steps, summary, head, (head_out.cpu().numpy(), status))
+
     # kept-source counts of a 200k-target subset (outside the timed region)
     sub = tgt[:min(M, 200000)].contiguous()
     grid = pcms.pcms_grid_build(src, pts_per_cell=0.7 ** 3 * p.k / (4.0 * np.pi / 3.0))
@@ -597,7 +641,8 @@ def main():
         orc = None
         if not args.no_cpu:
             import oracle as orc
-        result["other_configs"] = configs_leg(torch, pcms, synth, dev, args.steps, orc)
+        result["other_configs"] = configs_leg(torch, pcms, synth, dev, args.steps, orc,
+                                              lbvh=not args.no_lbvh)
 
     print(json.dumps(result), flush=True)
 

@@ -8,7 +8,9 @@
  * target t_i, the sources selected by a radial cut-off (Section 3.2.1's
  * selection function) are fitted by the weighted, Tikhonov-regularised
  * least-squares polynomial of total degree <= p, and the fit is evaluated at
- * t_i.  Sources are located with a uniform-grid search (Section 3.3).
+ * t_i.  Sources are located with a uniform-grid search or a linear
+ * bounding volume hierarchy (the two structures Section 3.3 compares); both
+ * give the same neighbour lists.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -121,12 +123,15 @@ typedef struct {
 
 #define PCMS_ASYNC 0x1u   /* return after enqueue; statuses land in opts.summary */
 #define PCMS_PROFILE 0x2u /* time the phases with HIP events (see pcms_last_phase_ms) */
+#define PCMS_LBVH 0x4u    /* pcms_mls_transfer, pcms_operator_build: locate sources with
+                             an LBVH (pcms_lbvh_build) instead of the uniform grid; calls
+                             on a prebuilt handle use the handle's structure */
 
 typedef struct {
     int32_t weight;           /* PCMS_WEIGHT_* */
     int32_t precision;        /* PCMS_FP64 / PCMS_MIXED / PCMS_MIXED_REFINE */
     double lambda;            /* Tikhonov parameter of Eq. 1, >= 0, in the radius-scaled basis */
-    uint32_t flags;           /* PCMS_ASYNC | PCMS_PROFILE */
+    uint32_t flags;           /* PCMS_ASYNC | PCMS_PROFILE | PCMS_LBVH (other bits: PCMS_ERR_ARG) */
     int32_t block;            /* threads per workgroup (one per target): 0 = library choice, else 64/128/256 */
     int32_t *summary;         /* device int32[4] or NULL: counts of statuses 1, 2, 3 and CAPPED */
 } pcms_mls_opts;
@@ -150,6 +155,29 @@ pcms_status pcms_grid_build(const double *src, int64_t n_src, int32_t dim, const
                             double cell_width, double pts_per_cell, pcms_stream_t stream,
                             pcms_grid **out);
 pcms_status pcms_grid_free(pcms_grid *grid);
+
+/* Build a linear bounding volume hierarchy over the sources (Section 3.3's
+ * alternative to the uniform grid) and return it as a pcms_grid handle that
+ * every call taking a grid accepts (pcms_neighbors, pcms_mls_transfer_grid,
+ * pcms_mls_transfer_grid_noalloc) and pcms_grid_free releases.  The sources
+ * are sorted by the 32-bit Morton code of their position in the bounding box
+ * (32 / dim bits per coordinate); the leaves are the largest subtrees of the
+ * radix tree over the sorted codes that hold at most max_leaf sources
+ * (aligned Morton cells: compact boxes at any density), and a binary radix
+ * tree over the leaves' codes joins them, with FP32 boxes rounded outward.
+ * max_leaf: 1..64, or 0 for the default (4; the one-shot PCMS_LBVH calls
+ * use the default unless the environment variable PCMS_LBVH_LEAF sets
+ * another).  A search visits the leaves within reach of its
+ * ball and applies the grid's selection to their sources, so neighbour lists
+ * and statuses are bitwise those of the uniform grid; fitted values agree to
+ * rounding (the moment sums run in Morton order instead of bucket order).
+ * inv_scale: HOST float64[dim] metric factors (NULL = all 1).  The handle
+ * holds its own sorted coordinates. */
+pcms_status pcms_lbvh_build(const double *src, int64_t n_src, int32_t dim, const double *inv_scale,
+                            int32_t max_leaf, pcms_stream_t stream, pcms_grid **out);
+
+/* 1 if the handle was built by pcms_lbvh_build, 0 otherwise (or NULL). */
+int32_t pcms_grid_is_lbvh(const pcms_grid *grid);
 
 /* Neighbour lists (Section 3.2.1 selection set, capped).  For target i:
  * nbr[i*k_cap + e], e < n_kept[i], are the kept original source indices in
@@ -200,7 +228,8 @@ typedef struct pcms_operator pcms_operator;
  * k_cap, or k + 8 for a KNN radius with k + 8 < k_cap); the coordinates are
  * not kept.  status [n_tgt] (may be NULL) and the return code are as for
  * pcms_mls_transfer; on such a status code *out is still set (failed targets
- * give NaN when applied). */
+ * give NaN when applied).  With PCMS_LBVH the search runs on an LBVH (same
+ * kept sources; weights equal to rounding). */
 pcms_status pcms_operator_build(const double *src, int64_t n_src, int32_t dim, const double *tgt,
                                 int64_t n_tgt, int32_t basis_degree, const pcms_radius *radius,
                                 int32_t k_cap, const double *inv_scale, const pcms_mls_opts *opts,
@@ -363,12 +392,14 @@ size_t pcms_noalloc_scratch_bytes(void);
 typedef struct {
     size_t grid_bytes;           /* a pcms_grid (held until pcms_grid_free) */
     size_t grid_build_bytes;     /* temporary, during pcms_grid_build */
-    size_t transfer_bytes;       /* peak temporary of pcms_mls_transfer */
+    size_t transfer_bytes;       /* peak temporary of pcms_mls_transfer (either structure) */
     size_t transfer_grid_bytes;  /* temporary of pcms_mls_transfer_grid (the
                                     work space pcms_mls_transfer_grid_noalloc
                                     needs, <= noalloc_limit to be accepted) */
     size_t operator_apply_bytes; /* temporary of pcms_operator_apply */
     size_t noalloc_limit;        /* PCMS_NOALLOC_SCRATCH_BYTES */
+    size_t lbvh_bytes;           /* a pcms_lbvh_build handle */
+    size_t lbvh_build_bytes;     /* temporary, during pcms_lbvh_build */
 } pcms_workspace;
 
 /* Fills *out (host) for the given sizes; host-only arithmetic, no HIP call.

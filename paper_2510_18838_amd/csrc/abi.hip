@@ -15,6 +15,7 @@
 #include <string>
 
 #include "fit.h"
+#include "bvh.h"
 #include "internal.h"
 
 namespace pcms {
@@ -77,6 +78,7 @@ pcms_status check_opts(const pcms_mls_opts *o)
         return arg_error("block must be 0, 64, 128 or 256");
     if ((o->flags & PCMS_ASYNC) && !o->summary)
         return arg_error("PCMS_ASYNC needs a device summary buffer");
+    if (o->flags & ~(PCMS_ASYNC | PCMS_PROFILE | PCMS_LBVH)) return arg_error("unknown flag bits");
     return PCMS_OK;
 }
 
@@ -96,6 +98,14 @@ void cell_spec(const pcms_radius *r, int dim, double *cell_width, double *pts_pe
         *pts_per_cell = pow(cf, dim) * r->k / unit_ball_volume(dim);
     else
         *cell_width = cf * r->r;
+}
+
+// Leaf size of the LBVHs the one-shot calls build (PCMS_LBVH_LEAF overrides).
+int lbvh_leaf_default()
+{
+    const char *env = getenv("PCMS_LBVH_LEAF");
+    const int v = env ? atoi(env) : 0;
+    return v >= 1 && v <= kBvhLeafMax ? v : kBvhLeaf;
 }
 
 // Reads {"block": B, "cell_factor": F} from a file written by pcms_autotune.
@@ -137,6 +147,7 @@ void grid_alloc_free(Grid *g)
     if (g->iperm) (void)hipFree(g->iperm);
     if (g->spts) (void)hipFree(g->spts);
     if (g->spts32) (void)hipFree(g->spts32);
+    if (g->bvh_nodes) (void)hipFree(g->bvh_nodes);
     delete g;
 }
 
@@ -301,19 +312,43 @@ struct TransferWs {
 }  // namespace
 
 // Arrays of a grid over n_src sources: parameters, cell starts, both
-// permutations, FP64 and FP32 coordinate records.
+// permutations, FP64 and FP32 coordinate records; for an LBVH a single
+// bucket and the tree's nodes.
 struct GridLayout {
-    size_t o_cs, o_perm, o_iperm, o_spts, o_s32, bytes;
-    GridLayout(int64_t n_src, int dim)
+    size_t o_cs, o_perm, o_iperm, o_spts, o_s32, o_bvh, bytes;
+    int cells;
+    GridLayout(int64_t n_src, int dim, bool lbvh = false)
     {
+        cells = lbvh ? 1 : cells_cap_for(n_src);
         o_cs = align256(sizeof(GridParams));
-        o_perm = o_cs + align256(sizeof(int) * ((size_t)cells_cap_for(n_src) + 1));
+        o_perm = o_cs + align256(sizeof(int) * ((size_t)cells + 1));
         o_iperm = o_perm + align256(sizeof(int) * (size_t)n_src);
         o_spts = o_iperm + align256(sizeof(int) * (size_t)n_src);
         o_s32 = o_spts + align256(sizeof(double) * (size_t)n_src * padded_dim(dim));
-        bytes = o_s32 + sizeof(float) * 2 * (size_t)n_src * dim;   // FP32 + fixed-point
+        o_bvh = o_s32 + align256(sizeof(float) * 2 * (size_t)n_src * dim);   // FP32 + fixed-point
+        bytes = o_bvh + (lbvh ? bvh_node_bytes(n_src, dim) : 0);
+    }
+    // Points g's arrays into the block at base.
+    void place(Grid &g, void *base, bool lbvh) const
+    {
+        char *b = (char *)base;
+        g.n_cells_cap = cells;
+        g.params = (GridParams *)b;
+        g.cell_start = (int *)(b + o_cs);
+        g.perm = (int *)(b + o_perm);
+        g.iperm = (int *)(b + o_iperm);
+        g.spts = (double *)(b + o_spts);
+        g.spts32 = (float *)(b + o_s32);
+        g.sq = reinterpret_cast<uint32_t *>(g.spts32 + (size_t)g.n_src * g.dim);
+        g.bvh_nodes = lbvh ? (float *)(b + o_bvh) : nullptr;
     }
 };
+
+// Scratch that build_lbvh_device takes while it runs.
+size_t lbvh_build_scratch_bytes(int64_t n_src)
+{
+    return grid_build_scratch_bytes(n_src) + 256 + sizeof(int) * bvh_link_ints(n_src);
+}
 
 size_t transfer_ws_bytes(int64_t n_src, int n_fields, int64_t n_tgt)
 {
@@ -417,13 +452,14 @@ int32_t pcms_phase_ms_sum(double *sum_ms, int32_t n, int32_t reset)
 
 const char *pcms_last_error(void) { return g_last_error.c_str(); }
 
-static pcms_status grid_create(int64_t n_src, int32_t dim, const double *inv_scale, Grid **out)
+static pcms_status grid_create(int64_t n_src, int32_t dim, const double *inv_scale, bool lbvh,
+                               Grid **out)
 {
     Grid *g = new (std::nothrow) Grid();
     if (!g) return PCMS_ERR_NOMEM;
     g->dim = dim;
     g->n_src = n_src;
-    g->n_cells_cap = cells_cap_for(n_src);
+    g->n_cells_cap = lbvh ? 1 : cells_cap_for(n_src);
     for (int k = 0; k < kMaxDim; ++k) g->g[k] = (inv_scale && k < dim) ? inv_scale[k] : 1.0;
     hipError_t e;
     if ((e = hipGetDevice(&g->device)) != hipSuccess ||
@@ -432,7 +468,8 @@ static pcms_status grid_create(int64_t n_src, int32_t dim, const double *inv_sca
         (e = hipMalloc(&g->perm, sizeof(int) * (size_t)n_src)) != hipSuccess ||
         (e = hipMalloc(&g->iperm, sizeof(int) * (size_t)n_src)) != hipSuccess ||
         (e = hipMalloc(&g->spts, sizeof(double) * (size_t)n_src * padded_dim(dim))) != hipSuccess ||
-        (e = hipMalloc(&g->spts32, sizeof(float) * 2 * (size_t)n_src * dim)) != hipSuccess) {
+        (e = hipMalloc(&g->spts32, sizeof(float) * 2 * (size_t)n_src * dim)) != hipSuccess ||
+        (lbvh && (e = hipMalloc(&g->bvh_nodes, bvh_node_bytes(n_src, dim))) != hipSuccess)) {
         grid_alloc_free(g);
         return hip_fail(e, "hipMalloc(grid)");
     }
@@ -456,7 +493,7 @@ pcms_status pcms_grid_build(const double *src, int64_t n_src, int32_t dim, const
     if (st != PCMS_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     Grid *g = nullptr;
-    st = grid_create(n_src, dim, inv_scale, &g);
+    st = grid_create(n_src, dim, inv_scale, false, &g);
     if (st != PCMS_OK) return st;
     st = build_grid_device(g, src, cell_width, pts_per_cell, s);
     if (st != PCMS_OK) {
@@ -465,6 +502,35 @@ pcms_status pcms_grid_build(const double *src, int64_t n_src, int32_t dim, const
     }
     *out = reinterpret_cast<pcms_grid *>(g);
     return PCMS_OK;
+}
+
+pcms_status pcms_lbvh_build(const double *src, int64_t n_src, int32_t dim, const double *inv_scale,
+                            int32_t max_leaf, pcms_stream_t stream, pcms_grid **out)
+{
+    if (!out) return arg_error("out is NULL");
+    *out = nullptr;
+    if (dim < 1 || dim > kMaxDim) return arg_error("dim must be in [1, 5]");
+    if (n_src < 1 || n_src >= ((int64_t)1 << 31) / 2) return arg_error("n_src must be in [1, 2^30)");
+    if (!src) return arg_error("src is NULL");
+    if (max_leaf < 0 || max_leaf > kBvhLeafMax) return arg_error("max_leaf must be in [0, 64]");
+    pcms_status st = check_scale(inv_scale, dim);
+    if (st != PCMS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Grid *g = nullptr;
+    if ((st = grid_create(n_src, dim, inv_scale, true, &g)) != PCMS_OK) return st;
+    if ((st = build_lbvh_device(g, src, max_leaf > 0 ? max_leaf : lbvh_leaf_default(), s)) !=
+        PCMS_OK) {
+        (void)hipStreamSynchronize(s);
+        grid_alloc_free(g);
+        return st;
+    }
+    *out = reinterpret_cast<pcms_grid *>(g);
+    return PCMS_OK;
+}
+
+int32_t pcms_grid_is_lbvh(const pcms_grid *grid)
+{
+    return grid && reinterpret_cast<const Grid *>(grid)->lbvh ? 1 : 0;
 }
 
 pcms_status pcms_grid_free(pcms_grid *grid)
@@ -511,17 +577,20 @@ pcms_status pcms_workspace_query(int64_t n_src, int32_t dim, int32_t n_fields, i
     if (n_src < 1 || n_src >= ((int64_t)1 << 31) / 2) return arg_error("n_src must be in [1, 2^30)");
     if (n_tgt < 0 || n_tgt >= ((int64_t)1 << 31) / 2) return arg_error("n_tgt must be in [0, 2^30)");
     if (n_fields < 1) return arg_error("n_fields must be >= 1");
-    const GridLayout G(n_src, dim);
+    const GridLayout G(n_src, dim), B(n_src, dim, true);
     const size_t build = grid_build_scratch_bytes(n_src);
+    const size_t bbuild = lbvh_build_scratch_bytes(n_src);
     const size_t xfer = transfer_ws_bytes(n_src, n_fields, n_tgt);
     out->grid_bytes = G.bytes;
     out->grid_build_bytes = build;
     out->transfer_grid_bytes = xfer;
     // the one-shot call keeps its grid for the whole call; the build's
     // scratch is released (stream-ordered) before the transfer's is taken
-    out->transfer_bytes = G.bytes + std::max(build, xfer);
+    out->transfer_bytes = std::max(G.bytes + std::max(build, xfer), B.bytes + std::max(bbuild, xfer));
     out->operator_apply_bytes = sizeof(double) * (size_t)n_src * padded_dim(n_fields);
     out->noalloc_limit = PCMS_NOALLOC_SCRATCH_BYTES;
+    out->lbvh_bytes = B.bytes;
+    out->lbvh_build_bytes = bbuild;
     return PCMS_OK;
 }
 
@@ -542,25 +611,21 @@ pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, con
     if ((st = profile_begin(opts, s)) != PCMS_OK) return st;
     double cw, ppc;
     cell_spec(radius, dim, &cw, &ppc);
-    // one-shot grid in stream-ordered scratch
+    const bool lbvh = opts && (opts->flags & PCMS_LBVH);
+    // one-shot grid (or LBVH) in stream-ordered scratch
     Grid g{};
     g.dim = dim;
     g.n_src = n_src;
-    g.n_cells_cap = cells_cap_for(n_src);
     for (int k = 0; k < kMaxDim; ++k) g.g[k] = (inv_scale && k < dim) ? inv_scale[k] : 1.0;
     PCMS_HIP(hipGetDevice(&g.device));
     Scratch sc;
     sc.s = s;
-    const GridLayout L(n_src, dim);
+    const GridLayout L(n_src, dim, lbvh);
     if ((st = scratch_alloc(&sc.p, L.bytes, s)) != PCMS_OK) return st;
-    g.params = (GridParams *)sc.p;
-    g.cell_start = (int *)((char *)sc.p + L.o_cs);
-    g.perm = (int *)((char *)sc.p + L.o_perm);
-    g.iperm = (int *)((char *)sc.p + L.o_iperm);
-    g.spts = (double *)((char *)sc.p + L.o_spts);
-    g.spts32 = (float *)((char *)sc.p + L.o_s32);
-    g.sq = reinterpret_cast<uint32_t *>(g.spts32 + (size_t)n_src * dim);
-    if ((st = build_grid_device(&g, src, cw, ppc, s)) != PCMS_OK) return st;
+    L.place(g, sc.p, lbvh);
+    st = lbvh ? build_lbvh_device(&g, src, lbvh_leaf_default(), s)
+              : build_grid_device(&g, src, cw, ppc, s);
+    if (st != PCMS_OK) return st;
     return transfer_on_grid(&g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts,
                             s, tgt_vals, status, nullptr);
 }
@@ -608,13 +673,14 @@ pcms_status pcms_operator_build(const double *src, int64_t n_src, int32_t dim, c
     if (!op) return PCMS_ERR_NOMEM;
     op->n_src = n_src;
     op->n_tgt = n_tgt;
-    // one-shot grid in stream-ordered scratch
+    // one-shot grid (or LBVH) in stream-ordered scratch
     double cw, ppc;
     cell_spec(radius, dim, &cw, &ppc);
+    const bool lbvh = (o.flags & PCMS_LBVH) != 0;
     Grid g{};
     g.dim = dim;
     g.n_src = n_src;
-    g.n_cells_cap = cells_cap_for(n_src);
+    g.n_cells_cap = lbvh ? 1 : cells_cap_for(n_src);
     for (int k = 0; k < kMaxDim; ++k) g.g[k] = (inv_scale && k < dim) ? inv_scale[k] : 1.0;
     PCMS_HIP(hipGetDevice(&g.device));
     LaunchSpec ls{&g, tgt, nullptr, n_tgt, *radius, k_cap, o.block, nullptr};
@@ -641,23 +707,15 @@ pcms_status pcms_operator_build(const double *src, int64_t n_src, int32_t dim, c
     };
     Scratch sc;
     sc.s = s;
-    size_t o_cs = (sizeof(GridParams) + 255) & ~(size_t)255;
-    size_t o_perm = o_cs + ((sizeof(int) * ((size_t)g.n_cells_cap + 1) + 255) & ~(size_t)255);
-    size_t o_iperm = o_perm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
-    size_t o_spts = o_iperm + ((sizeof(int) * (size_t)n_src + 255) & ~(size_t)255);
-    size_t o_s32 = o_spts + ((sizeof(double) * (size_t)n_src * padded_dim(dim) + 255) & ~(size_t)255);
-    size_t o_sum = o_s32 + ((sizeof(float) * 2 * (size_t)n_src * dim + 255) & ~(size_t)255);
+    const GridLayout L(n_src, dim, lbvh);
+    const size_t o_sum = align256(L.bytes);
     if ((st = scratch_alloc(&sc.p, o_sum + 64, s)) != PCMS_OK) return fail(st);
-    g.params = (GridParams *)sc.p;
-    g.cell_start = (int *)((char *)sc.p + o_cs);
-    g.perm = (int *)((char *)sc.p + o_perm);
-    g.iperm = (int *)((char *)sc.p + o_iperm);
-    g.spts = (double *)((char *)sc.p + o_spts);
-    g.spts32 = (float *)((char *)sc.p + o_s32);
-    g.sq = reinterpret_cast<uint32_t *>(g.spts32 + (size_t)n_src * dim);
+    L.place(g, sc.p, lbvh);
     int32_t *summary = async ? o.summary : (int32_t *)((char *)sc.p + o_sum);
     if ((st = zero_ints(summary, 4, s)) != PCMS_OK) return fail(st);
-    if ((st = build_grid_device(&g, src, cw, ppc, s)) != PCMS_OK) return fail(st);
+    st = lbvh ? build_lbvh_device(&g, src, lbvh_leaf_default(), s)
+              : build_grid_device(&g, src, cw, ppc, s);
+    if (st != PCMS_OK) return fail(st);
     he = hipMemcpyAsync(op->perm, g.perm, sizeof(int) * (size_t)n_src, hipMemcpyDeviceToDevice, s);
     if (he == hipSuccess)
         he = hipMemcpyAsync(op->iperm, g.iperm, sizeof(int) * (size_t)n_src, hipMemcpyDeviceToDevice, s);

@@ -30,9 +30,14 @@ using std::ceil;
 using std::sqrt;
 // Called by the emulation build when a lane addresses LDS words outside its own.
 [[noreturn]] void pcms_emu_lds_fault(int e, int words);
+// The HIP vector type the walks load records with.
+struct alignas(16) float4 {
+    float x, y, z, w;
+};
 // Work counters of the emulation build (rows walked, candidates tested, walks,
-// candidates of FP32 walks that needed their FP64 record).
-extern thread_local long long pcms_emu_rows, pcms_emu_cands, pcms_emu_walks, pcms_emu_exact;
+// candidates of FP32 walks that needed their FP64 record, LBVH records read).
+extern thread_local long long pcms_emu_rows, pcms_emu_cands, pcms_emu_walks, pcms_emu_exact,
+    pcms_emu_nodes;
 // Collective operations of a lane group, provided by the emulation driver:
 // the G lanes of a group run as G threads meeting at a barrier per operation.
 struct EmuGroup;

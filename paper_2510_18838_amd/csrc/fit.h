@@ -185,6 +185,7 @@ struct KArgs {
     const double *spts;
     const float *spts32;   // FP32 records of the sorted sources (mixed-precision walks)
     const uint32_t *sq;    // fixed-point records of the sorted sources (mixed-precision fits)
+    const float *bvh_nodes;  // LBVH records (the BVH kernels)
     const int *perm;
     const double *tgt;
     const int *tperm;
@@ -240,8 +241,8 @@ PCMS_HD inline int target_words(int mode, int k, int k_cap)
 // inside the radius, the number of kept list entries and r^2 (all uniform
 // across the group).  F32: the walks classify candidates from the FP32
 // records (same lists).
-template <int D, bool UNIT, int G, bool F32 = false>
-PCMS_HD PCMS_INLINE int select_target(Search<D, UNIT, G> &S, const KArgs &a, int &n_found,
+template <int D, bool UNIT, int G, bool F32 = false, class S_>
+PCMS_HD PCMS_INLINE int select_target(S_ &S, const KArgs &a, int &n_found,
                                       int &n_kept, double &r2)
 {
     int st = PCMS_TGT_OK;
@@ -281,11 +282,12 @@ PCMS_HD PCMS_INLINE void load_point(const double *__restrict__ x, int i, double 
 }
 
 // Neighbour list of the target at sorted slot i (original indices, ascending).
-template <int D, bool UNIT, int G>
+template <int D, bool UNIT, int G, bool BVH = false>
 PCMS_HD PCMS_INLINE int nbr_target(const KArgs &a, const GridParams &gp, int i, int *L, Grp<G> g)
 {
     const int ti = a.tperm[i];
-    Search<D, UNIT, G> S{gp, a.cs, a.spts, a.spts32, a.perm, {}, L, a.k_cap, a.words, g};
+    Search<D, UNIT, G, BVH> S{gp, a.cs, a.spts, a.spts32, a.perm, {}, L, a.k_cap, a.words, g,
+                              {a.bvh_nodes}};
     load_point<D>(a.tgt, ti, S.t);
     int n_found, n;
     double r2;
@@ -619,7 +621,7 @@ PCMS_HD PCMS_INLINE void write_fields(const KArgs &a, int ti, int l0, const doub
 // sorted positions, slot e of sorted target i at [e * n_tgt + i], and the
 // kept count at op_n[i] (-1 for a failed target); then fhat = sum_e N_e f_e
 // for any field.
-template <int D, int P, int PREC, bool UNIT, int G, bool EMIT = false>
+template <int D, int P, int PREC, bool UNIT, int G, bool EMIT = false, bool BVH = false>
 PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i, int *L, Grp<G> g)
 {
     constexpr bool MIXED = PREC != PCMS_FP64;
@@ -640,13 +642,14 @@ PCMS_HD PCMS_INLINE int xfer_target(const KArgs &a, const GridParams &gp, int i,
     using FP = FitPts<D, UNIT, false>;
     using RecQ = typename FQ::Rec;
     // small bases: the first refinement step of MIXED_REFINE rides on the
-    // evaluation pass (its FP32 field moments fit in registers)
-    // (the first kFused fields; their FP32 field moments fit in registers)
+    // evaluation pass of the first kFused fields (their FP32 field moments
+    // fit in registers)
     constexpr int kFused = 4;
     constexpr bool FUSED = REFINE && !EMIT && M <= 6;
     using Rec = typename FP::Rec;
     const int ti = a.tperm[i];
-    Search<D, UNIT, G> S{gp, a.cs, a.spts, a.spts32, a.perm, {}, L, a.k_cap, a.words, g};
+    Search<D, UNIT, G, BVH> S{gp, a.cs, a.spts, a.spts32, a.perm, {}, L, a.k_cap, a.words, g,
+                              {a.bvh_nodes}};
     load_point<D>(a.tgt, ti, S.t);
     int n_found, n;
     double r2;

@@ -437,10 +437,42 @@ size_t grid_build_scratch_bytes(int64_t n_src)
     return 256 + sort_scratch_bytes((int)n_src) + 64 * sizeof(double);
 }
 
+pcms_status source_bbox_params(Grid *grid, const double *src, double *gdev, long long *bb,
+                               double cell_width, double pts_per_cell, hipStream_t s)
+{
+    const int dim = grid->dim;
+    const int n = (int)grid->n_src;
+    PCMS_HIP(hipMemcpyAsync(gdev, grid->g, sizeof(double) * dim, hipMemcpyHostToDevice, s));
+    k_bbox_init<<<1, 64, 0, s>>>(bb, dim);
+    PCMS_HIP(hipGetLastError());
+    pcms_status st = bbox(dim, src, n, bb, s);
+    if (st != PCMS_OK) return st;
+    k_grid_params<<<1, 1, 0, s>>>(bb, dim, n, gdev, cell_width, pts_per_cell, grid->n_cells_cap,
+                                  grid->params);
+    PCMS_HIP(hipGetLastError());
+    return PCMS_OK;
+}
+
+pcms_status gather_records(Grid *grid, const double *src, hipStream_t s)
+{
+    const int n = (int)grid->n_src;
+    const int blocks = grid_blocks(n, 256);
+    switch (grid->dim) {
+#define PCMS_GATHER(DD)                                                                          \
+    case DD:                                                                                     \
+        k_gather_pts<DD><<<blocks, 256, 0, s>>>(src, grid->perm, grid->params, n, grid->spts,    \
+                                                grid->spts32, grid->sq, grid->iperm);            \
+        break;
+        PCMS_GATHER(1) PCMS_GATHER(2) PCMS_GATHER(3) PCMS_GATHER(4) PCMS_GATHER(5)
+#undef PCMS_GATHER
+    }
+    PCMS_HIP(hipGetLastError());
+    return PCMS_OK;
+}
+
 pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
                               double pts_per_cell, hipStream_t s)
 {
-    const int dim = grid->dim;
     const int n = (int)grid->n_src;
     size_t bytes = grid_build_scratch_bytes(n);
     void *raw = nullptr;
@@ -462,33 +494,16 @@ pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
     cur += sizeof(int) * (size_t)256 * nb;
     int *scan_scratch = (int *)cur;
 
-    PCMS_HIP(hipMemcpyAsync(gdev, grid->g, sizeof(double) * dim, hipMemcpyHostToDevice, s));
-    k_bbox_init<<<1, 64, 0, s>>>(bb, dim);
-    PCMS_HIP(hipGetLastError());
-    if ((st = bbox(dim, src, n, bb, s)) != PCMS_OK) return st;
-    k_grid_params<<<1, 1, 0, s>>>(bb, dim, n, gdev, cell_width, pts_per_cell, grid->n_cells_cap,
-                                  grid->params);
-    PCMS_HIP(hipGetLastError());
-    if ((st = bucket_keys(dim, grid->params, src, n, k0, grid->perm, grid_blocks(n, 256), s)) != PCMS_OK)
+    if ((st = source_bbox_params(grid, src, gdev, bb, cell_width, pts_per_cell, s)) != PCMS_OK)
+        return st;
+    if ((st = bucket_keys(grid->dim, grid->params, src, n, k0, grid->perm, grid_blocks(n, 256), s)) != PCMS_OK)
         return st;
     st = radix_sort(k0, grid->perm, k1, v1, n, key_bits(grid->n_cells_cap), hist, scan_scratch, s);
     if (st != PCMS_OK) return st;
     k_cell_start<<<grid_blocks((int64_t)grid->n_cells_cap + 1, 256), 256, 0, s>>>(
         grid->params, k0, n, grid->cell_start);
     PCMS_HIP(hipGetLastError());
-    {
-        const int blocks = grid_blocks(n, 256);
-        switch (dim) {
-#define PCMS_GATHER(DD)                                                                        \
-    case DD:                                                                                   \
-        k_gather_pts<DD><<<blocks, 256, 0, s>>>(src, grid->perm, grid->params, n, grid->spts,  \
-                                                grid->spts32, grid->sq, grid->iperm);          \
-        break;
-            PCMS_GATHER(1) PCMS_GATHER(2) PCMS_GATHER(3) PCMS_GATHER(4) PCMS_GATHER(5)
-#undef PCMS_GATHER
-        }
-    }
-    PCMS_HIP(hipGetLastError());
+    if ((st = gather_records(grid, src, s)) != PCMS_OK) return st;
     scratch_free(raw, s);
     return PCMS_OK;
 }
@@ -516,10 +531,14 @@ pcms_status sort_targets(const Grid *grid, const double *tgt, int64_t n_tgt, int
     int *hist = (int *)cur;
     cur += sizeof(int) * (size_t)256 * nb;
     int *scan_scratch = (int *)cur;
-    // tiled Morton order when its keys fit 32 bits, else bucket order
+    // tiled Morton order when its keys fit 32 bits, else bucket order; on an
+    // LBVH (one bucket) the Morton order of the tree's box
     const double bound = tile_key_bound((double)grid->n_cells_cap, grid->dim);
     int bits;
-    if (bound < 4294967295.0) {
+    if (grid->lbvh) {
+        if ((st = morton_keys(grid->dim, grid->params, tgt, n, k0, tperm, s)) != PCMS_OK) return st;
+        bits = 32;
+    } else if (bound < 4294967295.0) {
         const int blocks = grid_blocks(n, 256);
         switch (grid->dim) {
         case 1: k_target_keys<1><<<blocks, 256, 0, s>>>(grid->params, tgt, n, k0, tperm); break;
@@ -547,6 +566,13 @@ pcms_status sort_pairs(unsigned *k0, int *v0, unsigned *k1, int *v1, int n, int 
 {
     return radix_sort(k0, v0, k1, v1, n, bits, hist, scan_scratch, s);
 }
+
+pcms_status exclusive_scan(int *data, int n, int *scratch, hipStream_t s)
+{
+    return scan_exclusive(data, n, scratch, s);
+}
+
+size_t exclusive_scan_ints(int n) { return (size_t)scan_scratch_ints(n); }
 
 size_t sort_hist_ints(int n) { return (size_t)256 * ((n + kSortItems - 1) / kSortItems); }
 

@@ -27,6 +27,11 @@ struct Grid {
                           // by the fixed-point records sq (one allocation)
     uint32_t *sq;         // device [n_src * dim]: quantize(coordinate), packed
     int device;
+    // LBVH (lbvh != 0): one bucket holding the sources in Morton order, and
+    // the tree's records (bvh.h; room for the worst case of one leaf per
+    // source, the leaf count itself stays on the device)
+    int lbvh;
+    float *bvh_nodes;     // device [2 n_src - 1][bvh_stride(dim)]
 };
 
 // error plumbing ------------------------------------------------------------
@@ -51,6 +56,24 @@ pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
                               double pts_per_cell, hipStream_t s);
 // Stream-ordered scratch that build_grid_device takes while it runs.
 size_t grid_build_scratch_bytes(int64_t n_src);
+// The two stages build_grid_device shares with the LBVH build: the bounding
+// box and the GridParams of the sources (gdev: a device copy of the metric,
+// bb: the box keys, both scratch), and the sorted coordinate records and
+// inverse permutation from grid->perm.
+pcms_status source_bbox_params(Grid *grid, const double *src, double *gdev, long long *bb,
+                               double cell_width, double pts_per_cell, hipStream_t s);
+pcms_status gather_records(Grid *grid, const double *src, hipStream_t s);
+// LBVH over the sources (lbvh.hip): `grid` allocated with n_cells_cap = 1
+// and bvh_node_bytes() of records; leaves of at most max_leaf sources.
+pcms_status build_lbvh_device(Grid *grid, const double *src, int max_leaf, hipStream_t s);
+size_t bvh_node_bytes(int64_t n_src, int dim);
+size_t bvh_link_ints(int64_t n_src);   // build scratch of the tree passes
+// Exclusive scan of n ints in place; scratch holds exclusive_scan_ints(n).
+pcms_status exclusive_scan(int *data, int n, int *scratch, hipStream_t s);
+size_t exclusive_scan_ints(int n);
+// 32-bit Morton codes of points in the box of gp (keys) with their indices.
+pcms_status morton_keys(int dim, const GridParams *gp, const double *pts, int64_t n,
+                        unsigned *keys, int *vals, hipStream_t s);
 // Target ordering: tperm[i] = index of the target at sorted position i.  Its
 // sort buffers are `ws` (sort_targets_bytes(n_tgt) bytes, 256-byte aligned)
 // when given, else stream-ordered scratch.

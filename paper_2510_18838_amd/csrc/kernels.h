@@ -22,18 +22,25 @@ constexpr int kGroup = PCMS_LANES_PER_TARGET;
 using KernelFn = void (*)(KArgs);
 
 // Kernel of dimension D for (degree, precision, unit metric); defined in
-// mls_d<D>.hip.
+// mls_d<D>.hip, and the same on an LBVH in bvh_d<D>.hip.
 template <int D>
 KernelFn transfer_kernel(int degree, int precision, bool unit);
 template <int D>
 KernelFn nbr_kernel(bool unit);
-// The operator-emission variant of transfer_kernel; defined in op_d<D>.hip.
+template <int D>
+KernelFn transfer_kernel_bvh(int degree, int precision, bool unit);
+template <int D>
+KernelFn nbr_kernel_bvh(bool unit);
+// The operator-emission variant of transfer_kernel; defined in op_d<D>.hip,
+// and on an LBVH in bvh_op_d<D>.hip.
 template <int D>
 KernelFn operator_kernel(int degree, int precision, bool unit);
+template <int D>
+KernelFn operator_kernel_bvh(int degree, int precision, bool unit);
 
 namespace {
 
-template <int D, bool UNIT, int G>
+template <int D, bool UNIT, int G, bool BVH = false>
 __global__ void __launch_bounds__(256) k_neighbors(KArgs a)
 {
     extern __shared__ int lds[];
@@ -46,7 +53,7 @@ __global__ void __launch_bounds__(256) k_neighbors(KArgs a)
     int st = 0;
     if (active) {
         const GridParams gp = *a.gp;
-        st = nbr_target<D, UNIT, G>(a, gp, i, lds + slot * a.stride, g);
+        st = nbr_target<D, UNIT, G, BVH>(a, gp, i, lds + slot * a.stride, g);
     }
     add_summary(a.summary, st, active && g.q == 0);
 }
@@ -58,7 +65,7 @@ __global__ void __launch_bounds__(256) k_neighbors(KArgs a)
 template <int PREC>
 constexpr int waves_for() { return PREC == PCMS_MIXED_REFINE ? PCMS_WAVES_REFINE : 3; }
 
-template <int D, int P, int PREC, bool UNIT, int G>
+template <int D, int P, int PREC, bool UNIT, int G, bool BVH = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for<PREC>())))
 k_transfer(KArgs a)
 {
@@ -72,13 +79,13 @@ k_transfer(KArgs a)
     int st = 0;
     if (active) {
         const GridParams gp = *a.gp;
-        st = xfer_target<D, P, PREC, UNIT, G>(a, gp, i, lds + slot * a.stride, g);
+        st = xfer_target<D, P, PREC, UNIT, G, false, BVH>(a, gp, i, lds + slot * a.stride, g);
     }
     add_summary(a.summary, st, active && g.q == 0);
 }
 
 // The same kernel writing the transfer operator instead of field values.
-template <int D, int P, int PREC, bool UNIT, int G>
+template <int D, int P, int PREC, bool UNIT, int G, bool BVH = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for<PREC>())))
 k_operator(KArgs a)
 {
@@ -92,25 +99,25 @@ k_operator(KArgs a)
     int st = 0;
     if (active) {
         const GridParams gp = *a.gp;
-        st = xfer_target<D, P, PREC, UNIT, G, true>(a, gp, i, lds + slot * a.stride, g);
+        st = xfer_target<D, P, PREC, UNIT, G, true, BVH>(a, gp, i, lds + slot * a.stride, g);
     }
     add_summary(a.summary, st, active && g.q == 0);
 }
 
-template <int D, int P, bool UNIT>
+template <int D, int P, bool UNIT, bool BVH = false>
 KernelFn pick_prec(int precision)
 {
-    return precision == PCMS_FP64  ? (KernelFn)k_transfer<D, P, PCMS_FP64, UNIT, kGroup>
-         : precision == PCMS_MIXED ? (KernelFn)k_transfer<D, P, PCMS_MIXED, UNIT, kGroup>
-                                   : (KernelFn)k_transfer<D, P, PCMS_MIXED_REFINE, UNIT, kGroup>;
+    return precision == PCMS_FP64  ? (KernelFn)k_transfer<D, P, PCMS_FP64, UNIT, kGroup, BVH>
+         : precision == PCMS_MIXED ? (KernelFn)k_transfer<D, P, PCMS_MIXED, UNIT, kGroup, BVH>
+                                   : (KernelFn)k_transfer<D, P, PCMS_MIXED_REFINE, UNIT, kGroup, BVH>;
 }
 
-template <int D, int P, bool UNIT>
+template <int D, int P, bool UNIT, bool BVH = false>
 KernelFn pick_prec_op(int precision)
 {
-    return precision == PCMS_FP64  ? (KernelFn)k_operator<D, P, PCMS_FP64, UNIT, kGroup>
-         : precision == PCMS_MIXED ? (KernelFn)k_operator<D, P, PCMS_MIXED, UNIT, kGroup>
-                                   : (KernelFn)k_operator<D, P, PCMS_MIXED_REFINE, UNIT, kGroup>;
+    return precision == PCMS_FP64  ? (KernelFn)k_operator<D, P, PCMS_FP64, UNIT, kGroup, BVH>
+         : precision == PCMS_MIXED ? (KernelFn)k_operator<D, P, PCMS_MIXED, UNIT, kGroup, BVH>
+                                   : (KernelFn)k_operator<D, P, PCMS_MIXED_REFINE, UNIT, kGroup, BVH>;
 }
 
 }  // namespace
@@ -133,6 +140,38 @@ KernelFn pick_prec_op(int precision)
     {                                                                                  \
         return unit ? (KernelFn)k_neighbors<DD, true, kGroup>                          \
                     : (KernelFn)k_neighbors<DD, false, kGroup>;                        \
+    }
+
+#define PCMS_DEFINE_DIM_BVH(DD)                                                        \
+    template <>                                                                        \
+    KernelFn transfer_kernel_bvh<DD>(int degree, int precision, bool unit)             \
+    {                                                                                  \
+        if (unit)                                                                      \
+            return degree == 0 ? pick_prec<DD, 0, true, true>(precision)               \
+                 : degree == 1 ? pick_prec<DD, 1, true, true>(precision)               \
+                               : pick_prec<DD, 2, true, true>(precision);              \
+        return degree == 0 ? pick_prec<DD, 0, false, true>(precision)                  \
+             : degree == 1 ? pick_prec<DD, 1, false, true>(precision)                  \
+                           : pick_prec<DD, 2, false, true>(precision);                 \
+    }                                                                                  \
+    template <>                                                                        \
+    KernelFn nbr_kernel_bvh<DD>(bool unit)                                             \
+    {                                                                                  \
+        return unit ? (KernelFn)k_neighbors<DD, true, kGroup, true>                    \
+                    : (KernelFn)k_neighbors<DD, false, kGroup, true>;                  \
+    }
+
+#define PCMS_DEFINE_DIM_OPERATOR_BVH(DD)                                               \
+    template <>                                                                        \
+    KernelFn operator_kernel_bvh<DD>(int degree, int precision, bool unit)             \
+    {                                                                                  \
+        if (unit)                                                                      \
+            return degree == 0 ? pick_prec_op<DD, 0, true, true>(precision)            \
+                 : degree == 1 ? pick_prec_op<DD, 1, true, true>(precision)            \
+                               : pick_prec_op<DD, 2, true, true>(precision);           \
+        return degree == 0 ? pick_prec_op<DD, 0, false, true>(precision)               \
+             : degree == 1 ? pick_prec_op<DD, 1, false, true>(precision)               \
+                           : pick_prec_op<DD, 2, false, true>(precision);              \
     }
 
 #define PCMS_DEFINE_DIM_OPERATOR(DD)                                                   \

@@ -18,8 +18,18 @@ __global__ void k_zero_ints(int32_t *p, int n)
     if (i < n) p[i] = 0;
 }
 
-KernelFn xfer_for(int d, int p, int precision, bool unit)
+KernelFn xfer_for(int d, int p, int precision, bool unit, bool bvh)
 {
+    if (bvh) {
+        switch (d) {
+        case 1: return transfer_kernel_bvh<1>(p, precision, unit);
+        case 2: return transfer_kernel_bvh<2>(p, precision, unit);
+        case 3: return transfer_kernel_bvh<3>(p, precision, unit);
+        case 4: return transfer_kernel_bvh<4>(p, precision, unit);
+        case 5: return transfer_kernel_bvh<5>(p, precision, unit);
+        }
+        return nullptr;
+    }
     switch (d) {
     case 1: return transfer_kernel<1>(p, precision, unit);
     case 2: return transfer_kernel<2>(p, precision, unit);
@@ -30,8 +40,18 @@ KernelFn xfer_for(int d, int p, int precision, bool unit)
     return nullptr;
 }
 
-KernelFn op_for(int d, int p, int precision, bool unit)
+KernelFn op_for(int d, int p, int precision, bool unit, bool bvh)
 {
+    if (bvh) {
+        switch (d) {
+        case 1: return operator_kernel_bvh<1>(p, precision, unit);
+        case 2: return operator_kernel_bvh<2>(p, precision, unit);
+        case 3: return operator_kernel_bvh<3>(p, precision, unit);
+        case 4: return operator_kernel_bvh<4>(p, precision, unit);
+        case 5: return operator_kernel_bvh<5>(p, precision, unit);
+        }
+        return nullptr;
+    }
     switch (d) {
     case 1: return operator_kernel<1>(p, precision, unit);
     case 2: return operator_kernel<2>(p, precision, unit);
@@ -42,8 +62,18 @@ KernelFn op_for(int d, int p, int precision, bool unit)
     return nullptr;
 }
 
-KernelFn nbr_for(int d, bool unit)
+KernelFn nbr_for(int d, bool unit, bool bvh)
 {
+    if (bvh) {
+        switch (d) {
+        case 1: return nbr_kernel_bvh<1>(unit);
+        case 2: return nbr_kernel_bvh<2>(unit);
+        case 3: return nbr_kernel_bvh<3>(unit);
+        case 4: return nbr_kernel_bvh<4>(unit);
+        case 5: return nbr_kernel_bvh<5>(unit);
+        }
+        return nullptr;
+    }
     switch (d) {
     case 1: return nbr_kernel<1>(unit);
     case 2: return nbr_kernel<2>(unit);
@@ -83,6 +113,7 @@ KArgs base_args(const LaunchSpec &ls, int block)
     a.spts = ls.grid->spts;
     a.spts32 = ls.grid->spts32;
     a.sq = ls.grid->sq;
+    a.bvh_nodes = ls.grid->bvh_nodes;
     a.perm = ls.grid->perm;
     a.tgt = ls.tgt;
     a.tperm = ls.tperm;
@@ -121,7 +152,7 @@ pcms_status launch_neighbors(const LaunchSpec &ls, int32_t *nbr, int32_t *n_kept
     a.n_found = n_found;
     a.r2 = r2;
     a.status = status;
-    KernelFn fn = nbr_for(ls.grid->dim, unit_metric(ls.grid));
+    KernelFn fn = nbr_for(ls.grid->dim, unit_metric(ls.grid), ls.grid->lbvh != 0);
     const int launch = ((a.n_blocks + 7) / 8) * 8;
     const size_t shm = (size_t)(block / kGroup) * target_stride(ls) * sizeof(int);
     hipLaunchKernelGGL(fn, dim3(launch), dim3(block), shm, s, a);
@@ -144,7 +175,8 @@ pcms_status launch_transfer(const LaunchSpec &ls, const double *svals, int n_fie
     a.out = out;
     a.stage = stage;
     a.status = status;
-    KernelFn fn = xfer_for(ls.grid->dim, degree, precision, unit_metric(ls.grid));
+    KernelFn fn = xfer_for(ls.grid->dim, degree, precision, unit_metric(ls.grid),
+                           ls.grid->lbvh != 0);
     const int launch = ((a.n_blocks + 7) / 8) * 8;
     const size_t shm = (size_t)(block / kGroup) * target_stride(ls) * sizeof(int);
     hipLaunchKernelGGL(fn, dim3(launch), dim3(block), shm, s, a);
@@ -165,7 +197,8 @@ pcms_status launch_operator(const LaunchSpec &ls, int degree, int weight, int pr
     a.op_c = op_c;
     a.op_n = op_n;
     a.status = status;
-    KernelFn fn = op_for(ls.grid->dim, degree, precision, unit_metric(ls.grid));
+    KernelFn fn = op_for(ls.grid->dim, degree, precision, unit_metric(ls.grid),
+                         ls.grid->lbvh != 0);
     const int launch = ((a.n_blocks + 7) / 8) * 8;
     const size_t shm = (size_t)(block / kGroup) * target_stride(ls) * sizeof(int);
     hipLaunchKernelGGL(fn, dim3(launch), dim3(block), shm, s, a);

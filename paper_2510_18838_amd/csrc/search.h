@@ -20,6 +20,7 @@
 // order, which the ordered ballot compaction of the lists preserves.
 #pragma once
 
+#include "bvh.h"
 #include "device_common.h"
 
 namespace pcms {
@@ -236,13 +237,33 @@ struct Bins32 {
     }
 };
 
-// Calls f(p, x, valid) for every sorted source p in the buckets that can hold
-// a source with D < rho2 (a superset of the ball), x being the measure's value
-// (D, or its FP32 image), kBatch * G candidates per step (the loads of a step
-// are issued together); every lane of the
-// group calls f the same number of times, with valid = false on the padding
-// slots past a row's end.  rho2 may be +inf.  The next row's bucket offsets
-// are loaded while the current row is processed.
+// Calls f(p, x, valid) for the sorted sources p of [beg, end), x being the
+// measure's value (D, or its FP32 image), kBatch * G candidates per step (the
+// loads of a step are issued together); every lane of the group calls f the
+// same number of times, with valid = false on the padding slots past the end.
+template <int D, int G, int kBatch, class Meas, class F>
+PCMS_HD PCMS_INLINE void walk_range(const Meas &meas, int beg, int end, int q, F &&f)
+{
+    for (int p0 = beg; p0 < end; p0 += kBatch * G) {
+        // slot j of lane q is candidate p0 + j*G + q: the group's loads of
+        // one slot are contiguous
+        typename Meas::E sb[kBatch][D];
+        int pp[kBatch];
+        bool ok[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            pp[j] = p0 + j * G + q;
+            ok[j] = pp[j] < end;
+            meas.load(ok[j] ? pp[j] : beg, sb[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) f(pp[j], meas.d2(sb[j]), ok[j]);
+    }
+}
+
+// walk_range over every sorted source in the buckets that can hold a source
+// with D < rho2 (a superset of the ball).  rho2 may be +inf.  The next row's
+// bucket offsets are loaded while the current row is processed.
 template <int D, bool UNIT, int G, int kBatch, class Meas, class F>
 PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs, const Meas &meas,
                               const double (&t)[D], double rho2, int q, F &&f)
@@ -271,21 +292,7 @@ PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs, 
             pcms_emu_cands += end - beg;
         }
 #endif
-        for (int p0 = beg; p0 < end; p0 += kBatch * G) {
-            // slot j of lane q is candidate p0 + j*G + q: the group's loads of
-            // one slot are contiguous
-            typename Meas::E sb[kBatch][D];
-            int pp[kBatch];
-            bool ok[kBatch];
-#pragma unroll
-            for (int j = 0; j < kBatch; ++j) {
-                pp[j] = p0 + j * G + q;
-                ok[j] = pp[j] < end;
-                meas.load(ok[j] ? pp[j] : beg, sb[j]);
-            }
-#pragma unroll
-            for (int j = 0; j < kBatch; ++j) f(pp[j], meas.d2(sb[j]), ok[j]);
-        }
+        walk_range<D, G, kBatch>(meas, beg, end, q, f);
         beg = nbeg;
         end = nend;
         have = nhave;
@@ -295,7 +302,32 @@ PCMS_HD PCMS_INLINE void walk(const GridParams &gp, const int *__restrict__ cs, 
 // Search state of one target, shared by its G lanes.  The target's `words`
 // LDS words L[0..words) hold the kept list (k_cap entries) and, during the
 // radius search, a buffer of words / 2 doubles (double j in words 2j, 2j+1).
-template <int D, bool UNIT, int G>
+// The walk over the sources that can lie inside a ball: the grid's row walk,
+// or with BVH the leaves of the tree within reach (bvh.h).
+template <int D, bool UNIT, int G, bool BVH, int kBatch, class Meas, class F>
+PCMS_HD PCMS_INLINE void walk_any(const GridParams &gp, const int *__restrict__ cs,
+                                  const BvhView &bv, const Meas &meas, const double (&t)[D],
+                                  double rho2, int q, F &&f)
+{
+    if constexpr (BVH) {
+#ifdef PCMS_HOST_EMULATION
+        if (q == 0) ++pcms_emu_walks;
+#endif
+        bvh_leaves<D, UNIT>(gp, bv, t, rho2, [&](int beg, int end) {
+#ifdef PCMS_HOST_EMULATION
+            if (q == 0) {
+                ++pcms_emu_rows;
+                pcms_emu_cands += end - beg;
+            }
+#endif
+            walk_range<D, G, kBatch>(meas, beg, end, q, f);
+        });
+    } else {
+        walk<D, UNIT, G, kBatch>(gp, cs, meas, t, rho2, q, f);
+    }
+}
+
+template <int D, bool UNIT, int G, bool BVH = false>
 struct Search {
     const GridParams &gp;
     const int *__restrict__ cs;
@@ -307,6 +339,7 @@ struct Search {
     int k_cap;
     int words;  // >= max(k_cap, 2)
     Grp<G> g;
+    BvhView bv; // the tree (BVH only)
 
     PCMS_HD PCMS_INLINE int &at(int e)
     {
@@ -330,7 +363,8 @@ struct Search {
     template <class F>
     PCMS_HD PCMS_INLINE void each(double rho2, F &&f)
     {
-        walk<D, UNIT, G, kBatch64>(gp, cs, Exact64<D, UNIT>{gp, spts, t}, t, rho2, g.q, f);
+        walk_any<D, UNIT, G, BVH, kBatch64>(gp, cs, bv, Exact64<D, UNIT>{gp, spts, t}, t, rho2, g.q,
+                                            f);
     }
 
     // Calls f(p, bins(D), valid) for the candidates of the walk over rho2.
@@ -348,7 +382,7 @@ struct Search {
         }
         const Image32<D, UNIT> im(gp, spts32, t, c);
         const Bins32 b32(bins, im);
-        walk<D, UNIT, G, kBatch32>(gp, cs, im, t, rho2, g.q, [&](int p, float d32, bool ok) {
+        walk_any<D, UNIT, G, BVH, kBatch32>(gp, cs, bv, im, t, rho2, g.q, [&](int p, float d32, bool ok) {
             bool sure;
             int kk = b32(d32, sure);
             if (ok && !sure) {
@@ -401,6 +435,7 @@ struct Search {
     // around t (no point loads).
     PCMS_HD double knn_radius_guess(int k) const
     {
+        if constexpr (BVH) return bvh_radius_guess<D, UNIT>(gp, bv, t, k);
         int a[D], b[D], c[D];
         double vol = 1.0;
 #pragma unroll

@@ -31,6 +31,7 @@ WEIGHT_WENDLAND_C2, WEIGHT_C4, WEIGHT_GAUSSIAN, WEIGHT_CONST, WEIGHT_IMQ, WEIGHT
 FP64, MIXED, MIXED_REFINE = 0, 1, 2
 ASYNC = 0x1
 PROFILE = 0x2
+LBVH = 0x4
 
 EXPORTED = ("pcms_mls_opts_default", "pcms_grid_build", "pcms_grid_free", "pcms_neighbors",
             "pcms_mls_transfer", "pcms_mls_transfer_grid", "pcms_last_phase_ms", "pcms_version",
@@ -38,7 +39,8 @@ EXPORTED = ("pcms_mls_opts_default", "pcms_grid_build", "pcms_grid_free", "pcms_
             "pcms_batch_plan_exec", "pcms_batch_plan_free", "pcms_autotune",
             "pcms_operator_build", "pcms_operator_apply", "pcms_operator_export",
             "pcms_operator_width", "pcms_operator_free", "pcms_mls_transfer_grid_noalloc",
-            "pcms_noalloc_scratch_bytes", "pcms_workspace_query", "pcms_phase_ms_sum")
+            "pcms_noalloc_scratch_bytes", "pcms_workspace_query", "pcms_phase_ms_sum",
+            "pcms_lbvh_build", "pcms_grid_is_lbvh")
 
 
 class PcmsError(RuntimeError):
@@ -75,7 +77,8 @@ class BatchOpts(ctypes.Structure):
 class Workspace(ctypes.Structure):
     _fields_ = [("grid_bytes", ctypes.c_size_t), ("grid_build_bytes", ctypes.c_size_t),
                 ("transfer_bytes", ctypes.c_size_t), ("transfer_grid_bytes", ctypes.c_size_t),
-                ("operator_apply_bytes", ctypes.c_size_t), ("noalloc_limit", ctypes.c_size_t)]
+                ("operator_apply_bytes", ctypes.c_size_t), ("noalloc_limit", ctypes.c_size_t),
+                ("lbvh_bytes", ctypes.c_size_t), ("lbvh_build_bytes", ctypes.c_size_t)]
 
 
 class TuneResult(ctypes.Structure):
@@ -101,6 +104,10 @@ def lib() -> ctypes.CDLL:
     L.pcms_mls_opts_default.restype = None
     L.pcms_grid_build.argtypes = [P, i64, i32, P, dbl, dbl, P, ctypes.POINTER(P)]
     L.pcms_grid_build.restype = i32
+    L.pcms_lbvh_build.argtypes = [P, i64, i32, P, i32, P, ctypes.POINTER(P)]
+    L.pcms_lbvh_build.restype = i32
+    L.pcms_grid_is_lbvh.argtypes = [P]
+    L.pcms_grid_is_lbvh.restype = i32
     L.pcms_grid_free.argtypes = [P]
     L.pcms_grid_free.restype = i32
     L.pcms_neighbors.argtypes = [P, P, i64, ctypes.POINTER(Radius), i32, P, P, P, P, P, P]
@@ -269,10 +276,14 @@ def num_monomials(dim: int, degree: int) -> int:
 
 
 class Grid:
-    """Owning wrapper of a pcms_grid handle."""
+    """Owning wrapper of a pcms_grid handle (a uniform grid or an LBVH)."""
 
     def __init__(self, handle: ctypes.c_void_p, n_src: int, dim: int):
         self.handle, self.n_src, self.dim = handle, n_src, dim
+
+    @property
+    def is_lbvh(self) -> bool:
+        return bool(lib().pcms_grid_is_lbvh(self.handle))
 
     def free(self):
         if self.handle:
@@ -301,6 +312,18 @@ def pcms_grid_build(src: torch.Tensor, inv_scale=None, cell_width=0.0, pts_per_c
     h = ctypes.c_void_p()
     _check(lib().pcms_grid_build(_ptr(src), n, dim, g, float(cell_width), float(pts_per_cell),
                                  _stream(stream), ctypes.byref(h)))
+    return Grid(h, n, dim)
+
+
+def pcms_lbvh_build(src: torch.Tensor, inv_scale=None, max_leaf=0, stream=None) -> Grid:
+    """LBVH over the sources (leaves of at most max_leaf sources, 0 = the
+    library default), usable wherever a grid is."""
+    _points(src, "src")
+    n, dim = src.shape
+    keep, g = _host_scale(inv_scale, dim)
+    h = ctypes.c_void_p()
+    _check(lib().pcms_lbvh_build(_ptr(src), n, dim, g, int(max_leaf), _stream(stream),
+                                 ctypes.byref(h)))
     return Grid(h, n, dim)
 
 

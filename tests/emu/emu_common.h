@@ -43,7 +43,7 @@ struct EmuGroup {
     explicit EmuGroup(int g) : G(g), bar(g) {}
 };
 
-extern long long g_rows, g_cands, g_walks, g_exact;
+extern long long g_rows, g_cands, g_walks, g_exact, g_nodes;
 
 namespace emu {
 
@@ -75,6 +75,7 @@ void run_groups(const KArgs &a, Body body)
                 g_cands = pcms_emu_cands;
                 g_walks = pcms_emu_walks;
                 g_exact = pcms_emu_exact;
+                g_nodes = pcms_emu_nodes;
             }
         });
     }
@@ -101,13 +102,21 @@ void run_groups(const KArgs &a, Body body)
 template <int D, bool UNIT, int G>
 void run_nbr(const KArgs &a, const GridParams &gp)
 {
-    run_groups<G>(a, [&](int i, int *L, Grp<G> g) { nbr_target<D, UNIT, G>(a, gp, i, L, g); });
+    if (a.bvh_nodes)
+        run_groups<G>(a, [&](int i, int *L, Grp<G> g) { nbr_target<D, UNIT, G, true>(a, gp, i, L, g); });
+    else
+        run_groups<G>(a, [&](int i, int *L, Grp<G> g) { nbr_target<D, UNIT, G>(a, gp, i, L, g); });
 }
 
 template <int D, int P, int PREC, bool UNIT, int G>
 void run_xfer(const KArgs &a, const GridParams &gp)
 {
-    run_groups<G>(a, [&](int i, int *L, Grp<G> g) { xfer_target<D, P, PREC, UNIT, G>(a, gp, i, L, g); });
+    if (a.bvh_nodes)
+        run_groups<G>(a, [&](int i, int *L, Grp<G> g) {
+            xfer_target<D, P, PREC, UNIT, G, false, true>(a, gp, i, L, g);
+        });
+    else
+        run_groups<G>(a, [&](int i, int *L, Grp<G> g) { xfer_target<D, P, PREC, UNIT, G>(a, gp, i, L, g); });
 }
 
 template <int D, int P, int PREC, bool UNIT, int G>
@@ -150,5 +159,15 @@ inline void dispatch(int op, const KArgs &a, const GridParams &gp, int group, in
 template <int D>
 void dispatch_dim(int op, const KArgs &a, const GridParams &gp, int group, int degree,
                   int precision, bool unit);
+
+// LBVH steps (emu_dim.cpp), serial versions of the device build with its
+// per-item functions: Morton codes of n points in the single-bucket box of
+// gp; the tree over the sorted codes and sorted records spts (nodes sized
+// by the caller for 2n - 1 records, returns the leaf count; aborts on a
+// malformed tree).
+template <int D>
+void morton_keys(const GridParams &gp, const double *pts, int n, std::vector<unsigned> &keys);
+template <int D>
+int lbvh_tree(const unsigned *codes, int n, const double *spts, float *nodes);
 
 }  // namespace emu

@@ -17,7 +17,7 @@
 #include "emu_common.h"
 
 thread_local long long pcms_emu_rows = 0, pcms_emu_cands = 0, pcms_emu_walks = 0,
-                       pcms_emu_exact = 0;
+                       pcms_emu_exact = 0, pcms_emu_nodes = 0;
 
 unsigned pcms_emu_ballot(EmuGroup *g, int q, bool p)
 {
@@ -61,7 +61,7 @@ void pcms_emu_sync(EmuGroup *g, int q)
     g->bar.arrive_and_wait();
 }
 
-long long g_rows = 0, g_cands = 0, g_walks = 0, g_exact = 0;
+long long g_rows = 0, g_cands = 0, g_walks = 0, g_exact = 0, g_nodes = 0;
 
 [[noreturn]] void pcms_emu_lds_fault(int e, int words)
 {
@@ -191,7 +191,9 @@ int main(int argc, char **argv)
     if (!f) die("cannot open input");
     Reader rd{f};
     if (rd.i64() != 0x50434d53454d55LL) die("bad magic");
-    const int op = (int)rd.i64();
+    const int op_word = (int)rd.i64();
+    const int op = op_word & 0xf;
+    const bool lbvh = (op_word & 0x10) != 0;   // the LBVH in place of the uniform grid
     const int64_t n_src = rd.i64(), dim = rd.i64(), n_tgt = rd.i64(), nf = rd.i64();
     const int degree = (int)rd.i64(), mode = (int)rd.i64(), k = (int)rd.i64();
     const int n_min = (int)rd.i64(), max_iter = (int)rd.i64(), k_cap = (int)rd.i64();
@@ -214,23 +216,41 @@ int main(int argc, char **argv)
             hi[q] = std::fmax(hi[q], src[j * dim + q]);
         }
     }
-    const int cap = (int)std::min<int64_t>(2 * n_src + 64, (int64_t)1 << 30);
+    // an LBVH: one bucket over the box, sources in Morton order
+    const int cap = lbvh ? 1 : (int)std::min<int64_t>(2 * n_src + 64, (int64_t)1 << 30);
     GridParams gp;
-    grid_params_compute(lo, hi, (int)dim, n_src, g, cell_width, ppc, cap, &gp);
+    if (lbvh)
+        grid_params_compute(lo, hi, (int)dim, n_src, g, 0.0, (double)n_src, 1, &gp);
+    else
+        grid_params_compute(lo, hi, (int)dim, n_src, g, cell_width, ppc, cap, &gp);
     if (gp.n_cells > cap) die("bucket count above the allocation");
     std::vector<unsigned> keys(n_src);
     std::vector<int> perm(n_src);
-    for (int64_t j = 0; j < n_src; ++j) {
-        keys[j] = bucket_key(gp, &src[j * dim]);
-        perm[j] = (int)j;
-        if (keys[j] >= (unsigned)gp.n_cells) die("bucket key out of range");
+#define MORTON(DD)                                                              \
+    case DD:                                                                    \
+        emu::morton_keys<DD>(gp, src.data(), (int)n_src, keys);                 \
+        break;
+    if (lbvh) {
+        switch (dim) { MORTON(1) MORTON(2) MORTON(3) MORTON(4) MORTON(5) }
+        for (int64_t j = 0; j < n_src; ++j) perm[j] = (int)j;
+        radix_sort_emu(keys, perm, 32);
+    } else {
+        for (int64_t j = 0; j < n_src; ++j) {
+            keys[j] = bucket_key(gp, &src[j * dim]);
+            perm[j] = (int)j;
+            if (keys[j] >= (unsigned)gp.n_cells) die("bucket key out of range");
+        }
+        radix_sort_emu(keys, perm, key_bits(cap));
     }
-    radix_sort_emu(keys, perm, key_bits(cap));
     for (int64_t j = 1; j < n_src; ++j)
         if (keys[j - 1] > keys[j] || (keys[j - 1] == keys[j] && perm[j - 1] > perm[j]))
             die("radix sort is not stable-sorted");
     std::vector<int> cs((size_t)cap + 1, -1);
     for (int c = 0; c <= gp.n_cells; ++c) {
+        if (lbvh) {
+            cs[c] = c == 0 ? 0 : (int)n_src;
+            continue;
+        }
         int l = 0, h = (int)n_src;
         while (l < h) {
             int mid = (l + h) >> 1;
@@ -256,19 +276,45 @@ int main(int argc, char **argv)
     for (int64_t p = 0; p < n_src; ++p)
         for (int q = 0; q < dim; ++q)
             sq[p * dim + q] = quantize(src[(size_t)perm[p] * dim + q], gp.lo[q], gp.iqs[q]);
+    // the tree (records poisoned with NaN; lbvh_tree checks that every node
+    // is completed by both children and that the ropes chain the leaves)
+    // (16-byte aligned: the walks read records as float4)
+    std::vector<float4> node_store((size_t)bvh_stride((int)dim) * (2 * n_src - 1) / 4,
+                                   float4{NAN, NAN, NAN, NAN});
+    float *nodes = &node_store[0].x;
+    int n_leaves = 0;
+#define TREE(DD)                                                                 \
+    case DD:                                                                     \
+        n_leaves = emu::lbvh_tree<DD>(keys.data(), (int)n_src, spts.data(), nodes);   \
+        break;
+    if (lbvh) {
+        switch (dim) { TREE(1) TREE(2) TREE(3) TREE(4) TREE(5) }
+    }
     // targets, in the kernels' processing order
     std::vector<unsigned> tkeys(n_tgt);
     std::vector<int> tperm(n_tgt);
     const double bound = tile_key_bound((double)cap, dim);
     const bool tiled = bound < 4294967295.0;
-    for (int64_t i = 0; i < n_tgt; ++i) {
-        tkeys[i] = tiled ? target_key(gp, &tgt[i * dim]) : bucket_key(gp, &tgt[i * dim]);
-        tperm[i] = (int)i;
-    }
     int tbits = key_bits(cap);
-    if (tiled) {
-        tbits = 0;
-        while (tbits < 32 && (double)(1ull << tbits) < bound) ++tbits;
+    if (lbvh) {
+        switch (dim) {
+#define TMORTON(DD)                                                              \
+    case DD:                                                                     \
+        emu::morton_keys<DD>(gp, tgt.data(), (int)n_tgt, tkeys);                 \
+        break;
+            TMORTON(1) TMORTON(2) TMORTON(3) TMORTON(4) TMORTON(5)
+        }
+        for (int64_t i = 0; i < n_tgt; ++i) tperm[i] = (int)i;
+        tbits = 32;
+    } else {
+        for (int64_t i = 0; i < n_tgt; ++i) {
+            tkeys[i] = tiled ? target_key(gp, &tgt[i * dim]) : bucket_key(gp, &tgt[i * dim]);
+            tperm[i] = (int)i;
+        }
+        if (tiled) {
+            tbits = 0;
+            while (tbits < 32 && (double)(1ull << tbits) < bound) ++tbits;
+        }
     }
     radix_sort_emu(tkeys, tperm, tbits);
     const int nfs = padded_dim((int)nf);
@@ -282,6 +328,8 @@ int main(int argc, char **argv)
     a.spts = spts.data();
     a.spts32 = spts32.data();
     a.sq = sq.data();
+    a.bvh_nodes = lbvh ? nodes : nullptr;
+    if (lbvh) std::fprintf(stderr, "lbvh: %d leaves over %lld sources\n", n_leaves, (long long)n_src);
     a.perm = perm.data();
     a.tgt = tgt.data();
     a.tperm = tperm.data();
@@ -343,6 +391,7 @@ int main(int argc, char **argv)
                  " exact rechecks %.3f\n",
                  g_walks, g_rows, g_cands, (double)g_walks / n_tgt, (double)g_rows / n_tgt,
                  (double)g_cands / n_tgt, (double)g_exact / n_tgt);
+    if (lbvh) std::fprintf(stderr, "lbvh records visited per target: %.2f\n", (double)g_nodes / n_tgt);
     FILE *o = std::fopen(argv[2], "wb");
     if (!o) die("cannot open output");
     if (op == 0) {

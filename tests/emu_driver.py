@@ -20,7 +20,7 @@ SRC = os.path.join(EMU_DIR, "pcms_emu.cpp")
 EXE = os.path.join(EMU_DIR, "pcms_emu")
 DEPS = [SRC, os.path.join(EMU_DIR, "emu_common.h"), os.path.join(EMU_DIR, "emu_dim.cpp")] + \
        [os.path.join(ROOT, "paper_2510_18838_amd", "csrc", f)
-                for f in ("device_common.h", "search.h", "fit.h")] + \
+                for f in ("device_common.h", "search.h", "fit.h", "bvh.h")] + \
        [os.path.join(ROOT, "include", "pcms_mls.h")]
 
 
@@ -61,10 +61,11 @@ def _cell_spec(prob):
     return cf * prob.radius, 0.0
 
 
-def run(prob, op, precision=0, weight=0, lam=0.0, group=1, tgt=None):
+def run(prob, op, precision=0, weight=0, lam=0.0, group=1, tgt=None, lbvh=False):
     """op 0: neighbour lists; op 1: transfer; op 2: transfer operator (shape
     functions, original target order); group: lanes per target (1, as
-    in the kernels, or 4).  Returns a dict like the GPU helpers."""
+    in the kernels, or 4); lbvh: locate sources with the LBVH instead of the
+    uniform grid (ops 0 and 1).  Returns a dict like the GPU helpers."""
     exe = build()
     t = prob.tgt if tgt is None else tgt
     n_src, dim = prob.src.shape
@@ -74,7 +75,7 @@ def run(prob, op, precision=0, weight=0, lam=0.0, group=1, tgt=None):
     g = np.ones(5)
     if prob.inv_scale is not None:
         g[:dim] = prob.inv_scale
-    hdr = np.array([0x50434d53454d55, op, n_src, dim, n_tgt, nf, prob.degree, prob.mode, prob.k,
+    hdr = np.array([0x50434d53454d55, op | (0x10 if lbvh else 0), n_src, dim, n_tgt, nf, prob.degree, prob.mode, prob.k,
                     prob.n_min, prob.max_iter, prob.k_cap, weight, precision, group], np.int64)
     dbl = np.array([prob.radius, lam, cw, ppc, *g], np.float64)
     with tempfile.TemporaryDirectory() as d:

@@ -92,6 +92,8 @@ def test_transfer_rejects_bad_options():
     assert _transfer(o=o) == pcms.PCMS_ERR_ARG and "summary" in pcms.last_error()
     g = (ctypes.c_double * 2)(1.0, -2.0)
     assert _transfer(g=ctypes.cast(g, ctypes.c_void_p)) == pcms.PCMS_ERR_ARG
+    o = pcms.opts(flags=0x80)
+    assert _transfer(o=o) == pcms.PCMS_ERR_ARG and "flag" in pcms.last_error()
 
 
 @needs_lib
@@ -112,6 +114,16 @@ def test_grid_and_neighbor_argument_checks():
     assert L.pcms_mls_transfer_grid(None, FAKE, 1, FAKE, 5, 1, ctypes.byref(r), 8, None, None,
                                     FAKE, None) == pcms.PCMS_ERR_ARG
     assert L.pcms_grid_free(None) == pcms.PCMS_OK
+    assert L.pcms_lbvh_build(FAKE, 10, 6, None, 0, None, ctypes.byref(h)) == pcms.PCMS_ERR_ARG
+    assert L.pcms_lbvh_build(None, 10, 2, None, 0, None, ctypes.byref(h)) == pcms.PCMS_ERR_ARG
+    assert L.pcms_lbvh_build(FAKE, 0, 2, None, 0, None, ctypes.byref(h)) == pcms.PCMS_ERR_ARG
+    bad = (ctypes.c_double * 2)(1.0, 0.0)
+    assert L.pcms_lbvh_build(FAKE, 10, 2, ctypes.cast(bad, ctypes.c_void_p), 0, None,
+                             ctypes.byref(h)) == pcms.PCMS_ERR_ARG
+    assert L.pcms_lbvh_build(FAKE, 10, 2, None, 0, None, None) == pcms.PCMS_ERR_ARG
+    assert L.pcms_lbvh_build(FAKE, 10, 2, None, 65, None, ctypes.byref(h)) == pcms.PCMS_ERR_ARG
+    assert L.pcms_lbvh_build(FAKE, 10, 2, None, -1, None, ctypes.byref(h)) == pcms.PCMS_ERR_ARG
+    assert L.pcms_grid_is_lbvh(None) == 0
 
 
 def _problem(**kw):
@@ -281,6 +293,12 @@ def test_workspace_query():
     assert w["transfer_bytes"] >= w["grid_bytes"] + w["transfer_grid_bytes"]
     assert w["operator_apply_bytes"] == n_src * nf * 8
     assert w["noalloc_limit"] == pcms.lib().pcms_noalloc_scratch_bytes() == 128 << 20
+    # the LBVH: one bucket instead of the grid's, plus (n_src / 8 - 1) nodes of
+    # 16 floats in 3-D
+    nodes = (n_src // 8 - 1) * 16 * 4
+    assert w["lbvh_bytes"] >= n_src * (4 * 8 + 3 * 4 + 2 * 4) + nodes
+    assert w["lbvh_build_bytes"] >= n_src * 12
+    assert w["transfer_bytes"] >= w["lbvh_bytes"] + w["transfer_grid_bytes"]
     w2 = pcms.pcms_workspace_query(n_src, dim, nf + 1, n_tgt)   # odd counts pad to even
     assert w2["operator_apply_bytes"] == n_src * (nf + 2) * 8
     for bad in ((0, 3, 1, 1), (10, 0, 1, 1), (10, 6, 1, 1), (10, 3, 0, 1), (10, 3, 1, -1)):

@@ -28,11 +28,12 @@ class Sampled:
         return dict(out=out[:, self.idx], status=st[self.idx])
 
 
-def full_transfer(prob, precision):
+def full_transfer(prob, precision, lbvh=False):
     src, vals, tgt = dev(prob.src), dev(prob.vals), dev(prob.tgt)
     out, st, _ = pcms.pcms_mls_transfer(src, vals, tgt, prob.degree, pcms.radius_of(prob),
                                         prob.k_cap, inv_scale=prob.inv_scale,
-                                        o=pcms.opts(precision=precision))
+                                        o=pcms.opts(precision=precision,
+                                                    flags=pcms.LBVH if lbvh else 0))
     torch.cuda.synchronize()
     return out.cpu().numpy(), st.cpu().numpy()
 
@@ -46,12 +47,12 @@ def check_everywhere(out, st, where):
     assert np.isnan(out[:, ~ok]).all(), f"{where}: failed targets not NaN"
 
 
-def run_full(prob, precisions, n_sample, n_lists, seed):
-    say(f"{prob.name}: n_src={prob.src.shape[0]} n_tgt={prob.tgt.shape[0]} d={prob.dim} "
-        f"p={prob.degree} nf={prob.n_fields}")
+def run_full(prob, precisions, n_sample, n_lists, seed, lbvh=False):
+    say(f"{prob.name}{' on the LBVH' if lbvh else ''}: n_src={prob.src.shape[0]} "
+        f"n_tgt={prob.tgt.shape[0]} d={prob.dim} p={prob.degree} nf={prob.n_fields}")
     results = {}
     for prec in precisions:
-        out, st = full_transfer(prob, prec)
+        out, st = full_transfer(prob, prec, lbvh)
         check_everywhere(out, st, f"{prob.name} precision {prec}")
         results[prec] = (out, st)
         say(f"  precision {prec}: {int(((st & 0xF) == 0).sum())} valid targets, "
@@ -71,7 +72,7 @@ def run_full(prob, precisions, n_sample, n_lists, seed):
 
     class Lists:
         def neighbors(self, _):
-            return gpu_neighbors(prob, rows=rows)
+            return gpu_neighbors(prob, rows=rows, lbvh=lbvh)
 
     C.check_lists(Lists(), sub_l, f"{prob.name} full lists, {len(rows)} sampled")
 
@@ -87,6 +88,17 @@ def test_full_c2():
 
 def test_full_c5():
     run_full(synth.c5(), (pcms.FP64, pcms.MIXED_REFINE), n_sample=1500, n_lists=800, seed=35)
+
+
+def test_full_c5_lbvh():
+    """The 5-D workload on the LBVH, in the configuration bench.py times for
+    that backend."""
+    run_full(synth.c5(), (pcms.FP64, pcms.MIXED_REFINE), n_sample=1500, n_lists=800, seed=36,
+             lbvh=True)
+
+
+def test_full_c3_lbvh():
+    run_full(synth.c3(), (pcms.MIXED_REFINE,), n_sample=2000, n_lists=1000, seed=37, lbvh=True)
 
 
 def test_full_batch_c4():
