@@ -91,30 +91,37 @@ def time_transfer(torch, pcms, p, src, vals, tgt, rad, precision, steps, warmup,
                   summary, lbvh=False):
     """K one-shot transfers enqueued back to back (PCMS_ASYNC, statuses into a
     device summary), bracketed by device synchronisations: ms per step from
-    the host clock over the K steps, each step's duration from HIP events
-    recorded on the launch stream (median, min), and the phases' HIP-event
-    times inside the library (PCMS_PROFILE, averaged over the K steps).
-    lbvh: each step builds an LBVH instead of the uniform grid."""
-    flags = pcms.PROFILE | pcms.ASYNC | (pcms.LBVH if lbvh else 0)
-    o = pcms.opts(precision=precision, flags=flags, summary=summary)
+    the host clock over the K steps and each step's duration from HIP events
+    recorded on the launch stream (median, min).  Then the same K steps with
+    PCMS_PROFILE for the phases' HIP-event times inside the library
+    (averaged): a profiled call runs its phases one after the other, while
+    the timed calls order the targets beside the grid build and field
+    gather, so the phases of the profiled steps add up to a little more than
+    the timed step.  lbvh: each step builds an LBVH instead of the grid."""
+    extra = pcms.LBVH if lbvh else 0
+    o = pcms.opts(precision=precision, flags=pcms.ASYNC | extra, summary=summary)
+    op = pcms.opts(precision=precision, flags=pcms.PROFILE | pcms.ASYNC | extra, summary=summary)
 
-    def call():
+    def call(opts):
         pcms.pcms_mls_transfer(src, vals, tgt, p.degree, rad, p.k_cap, inv_scale=p.inv_scale,
-                               o=o, out=out, status=st)
+                               o=opts, out=out, status=st)
     for _ in range(warmup):
-        call()
+        call(o)
     torch.cuda.synchronize()
-    pcms.phase_ms_sum(reset=True)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
     t0 = time.perf_counter()
     for e0, e1 in ev:
         e0.record()
-        call()
+        call(o)
         e1.record()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     per = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    pcms.phase_ms_sum(reset=True)
+    for _ in range(steps):
+        call(op)
+    torch.cuda.synchronize()
     calls, sums = pcms.phase_ms_sum(reset=True)
     phases = {k: v / max(calls, 1) for k, v in sums.items()}
     return {"ms_per_step": ms, "ms_median": float(np.median(per)), "ms_min": float(per[0]),

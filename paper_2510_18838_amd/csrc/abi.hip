@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstring>
 #include <memory>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <string>
@@ -341,6 +342,7 @@ struct GridLayout {
         g.spts32 = (float *)(b + o_s32);
         g.sq = reinterpret_cast<uint32_t *>(g.spts32 + (size_t)g.n_src * g.dim);
         g.bvh_nodes = lbvh ? (float *)(b + o_bvh) : nullptr;
+        g.lbvh = lbvh ? 1 : 0;
     }
 };
 
@@ -355,10 +357,63 @@ size_t transfer_ws_bytes(int64_t n_src, int n_fields, int64_t n_tgt)
     return TransferWs(n_src, n_fields, n_tgt).bytes;
 }
 
+void transfer_ws_order(void *ws, int64_t n_src, int n_fields, int64_t n_tgt, int **tperm,
+                       void **sort_ws)
+{
+    const TransferWs L(n_src, n_fields, n_tgt);
+    *tperm = (int *)((char *)ws + L.off_tperm);
+    *sort_ws = (char *)ws + L.off_sort;
+}
+
+namespace {
+// The calling thread's side stream on each device, with its fork and join
+// events; created on first use and kept for the life of the thread (never
+// destroyed: the runtime may already be gone when a thread's storage is).
+struct Side {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int kSideDevices = 64;
+thread_local Side g_side[kSideDevices];
+
+pcms_status side_stream(Side **out)
+{
+    int dev = 0;
+    PCMS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kSideDevices) {
+        set_error("device ordinal " + std::to_string(dev) + " beyond the supported 64");
+        return PCMS_ERR_ARG;
+    }
+    Side &sd = g_side[dev];
+    if (!sd.s) {
+        PCMS_HIP(hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking));
+        PCMS_HIP(hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming));
+        PCMS_HIP(hipEventCreateWithFlags(&sd.join, hipEventDisableTiming));
+    }
+    *out = &sd;
+    return PCMS_OK;
+}
+}  // namespace
+
+pcms_status order_targets_aside(const Grid *g, const double *tgt, int64_t n_tgt, int *tperm,
+                                void *sort_ws, hipStream_t s, hipEvent_t *join)
+{
+    Side *sd = nullptr;
+    pcms_status st = side_stream(&sd);
+    if (st != PCMS_OK) return st;
+    PCMS_HIP(hipEventRecord(sd->fork, s));
+    PCMS_HIP(hipStreamWaitEvent(sd->s, sd->fork, 0));
+    if ((st = sort_targets(g, tgt, n_tgt, tperm, sd->s, sort_ws)) != PCMS_OK) return st;
+    PCMS_HIP(hipEventRecord(sd->join, sd->s));
+    *join = sd->join;
+    return PCMS_OK;
+}
+
 pcms_status transfer_on_grid(const Grid *g, const double *src_vals, int32_t n_fields,
                              const double *tgt, int64_t n_tgt, int32_t degree,
                              const pcms_radius *radius, int32_t k_cap, const pcms_mls_opts *opts,
-                             hipStream_t s, double *tgt_vals, uint8_t *status, void *ws)
+                             hipStream_t s, double *tgt_vals, uint8_t *status, void *ws,
+                             bool overlap, hipEvent_t ordered)
 {
     pcms_mls_opts o;
     pcms_mls_opts_default(&o);
@@ -378,10 +433,20 @@ pcms_status transfer_on_grid(const Grid *g, const double *src_vals, int32_t n_fi
     double *stage = (double *)((char *)ws + L.off_stage);
     if ((st = zero_ints(summary, 4, s)) != PCMS_OK) return st;
     if ((st = g_prof.mark(1)) != PCMS_OK) return st;
-    if ((st = sort_targets(g, tgt, n_tgt, tperm, s, (char *)ws + L.off_sort)) != PCMS_OK) return st;
+    // the target order: forked off already, forked off now (to overlap the
+    // field gather), or in line
+    hipEvent_t join = ordered;
+    if (!join && overlap) {
+        st = order_targets_aside(g, tgt, n_tgt, tperm, (char *)ws + L.off_sort, s, &join);
+        if (st != PCMS_OK) return st;
+    } else if (!join) {
+        if ((st = sort_targets(g, tgt, n_tgt, tperm, s, (char *)ws + L.off_sort)) != PCMS_OK)
+            return st;
+    }
     if ((st = g_prof.mark(2)) != PCMS_OK) return st;
     if ((st = gather_values(g, src_vals, n_fields, svals, s)) != PCMS_OK) return st;
     if ((st = g_prof.mark(3)) != PCMS_OK) return st;
+    if (join) PCMS_HIP(hipStreamWaitEvent(s, join, 0));
     LaunchSpec ls{g, tgt, tperm, n_tgt, *radius, k_cap, o.block, summary};
     st = launch_transfer(ls, svals, n_fields, degree, o.weight, o.precision, o.lambda, tgt_vals,
                          stage, status, s);
@@ -584,9 +649,10 @@ pcms_status pcms_workspace_query(int64_t n_src, int32_t dim, int32_t n_fields, i
     out->grid_bytes = G.bytes;
     out->grid_build_bytes = build;
     out->transfer_grid_bytes = xfer;
-    // the one-shot call keeps its grid for the whole call; the build's
-    // scratch is released (stream-ordered) before the transfer's is taken
-    out->transfer_bytes = std::max(G.bytes + std::max(build, xfer), B.bytes + std::max(bbuild, xfer));
+    // the one-shot call keeps its grid for the whole call, and takes the
+    // transfer's workspace before the build's scratch is released (the
+    // target order runs beside the build)
+    out->transfer_bytes = std::max(G.bytes + build + xfer, B.bytes + bbuild + xfer);
     out->operator_apply_bytes = sizeof(double) * (size_t)n_src * padded_dim(n_fields);
     out->noalloc_limit = PCMS_NOALLOC_SCRATCH_BYTES;
     out->lbvh_bytes = B.bytes;
@@ -618,16 +684,32 @@ pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, con
     g.n_src = n_src;
     for (int k = 0; k < kMaxDim; ++k) g.g[k] = (inv_scale && k < dim) ? inv_scale[k] : 1.0;
     PCMS_HIP(hipGetDevice(&g.device));
-    Scratch sc;
-    sc.s = s;
+    Scratch sc, xs;
+    sc.s = xs.s = s;
     const GridLayout L(n_src, dim, lbvh);
     if ((st = scratch_alloc(&sc.p, L.bytes, s)) != PCMS_OK) return st;
     L.place(g, sc.p, lbvh);
-    st = lbvh ? build_lbvh_device(&g, src, lbvh_leaf_default(), s)
-              : build_grid_device(&g, src, cw, ppc, s);
+    // unprofiled calls order the targets on the side stream as soon as the
+    // grid's parameters exist, overlapping the rest of the build and the
+    // field gather (profiled calls run the phases in line, to time them)
+    hipEvent_t ordered = nullptr;
+    std::function<pcms_status()> fork;
+    if (!g_prof.on) {
+        if ((st = scratch_alloc(&xs.p, transfer_ws_bytes(n_src, n_fields, n_tgt), s)) != PCMS_OK)
+            return st;
+        fork = [&]() {
+            int *tperm;
+            void *sort_ws;
+            transfer_ws_order(xs.p, n_src, n_fields, n_tgt, &tperm, &sort_ws);
+            return order_targets_aside(&g, tgt, n_tgt, tperm, sort_ws, s, &ordered);
+        };
+    }
+    const std::function<pcms_status()> *hook = g_prof.on ? nullptr : &fork;
+    st = lbvh ? build_lbvh_device(&g, src, lbvh_leaf_default(), s, hook)
+              : build_grid_device(&g, src, cw, ppc, s, hook);
     if (st != PCMS_OK) return st;
     return transfer_on_grid(&g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts,
-                            s, tgt_vals, status, nullptr);
+                            s, tgt_vals, status, xs.p, !g_prof.on, ordered);
 }
 
 pcms_status pcms_mls_transfer_grid(const pcms_grid *grid, const double *src_vals, int32_t n_fields,
@@ -645,7 +727,7 @@ pcms_status pcms_mls_transfer_grid(const pcms_grid *grid, const double *src_vals
     if ((st = profile_begin(opts, (hipStream_t)stream)) != PCMS_OK) return st;
     if ((st = g_prof.mark(1)) != PCMS_OK) return st;   // no grid build in this call
     return transfer_on_grid(g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts,
-                            (hipStream_t)stream, tgt_vals, status, nullptr);
+                            (hipStream_t)stream, tgt_vals, status, nullptr, !g_prof.on);
 }
 
 pcms_status pcms_operator_build(const double *src, int64_t n_src, int32_t dim, const double *tgt,

@@ -7,6 +7,7 @@
 // and the whole layout is deterministic.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdlib.h>
 
 #include <algorithm>
 
@@ -302,17 +303,18 @@ int key_bits(int n_cells_cap)
     return b;
 }
 
-// Sorts (keys, vals) stably by key; the result ends up in (k0, v0).
+// Sorts (keys, vals) stably by key bits [lo_bit, bits); the result ends up
+// in (k0, v0).
 pcms_status radix_sort(unsigned *k0, int *v0, unsigned *k1, int *v1, int n, int bits, int *hist,
-                       int *scan_scratch, hipStream_t s)
+                       int *scan_scratch, hipStream_t s, int lo_bit = 0)
 {
     int nb = (n + kSortItems - 1) / kSortItems;
     if (nb == 0) return PCMS_OK;
-    int passes = std::max(1, (bits + 7) / 8);
+    int passes = std::max(1, (bits - lo_bit + 7) / 8);
     unsigned *kin = k0, *kout = k1;
     int *vin = v0, *vout = v1;
     for (int ps = 0; ps < passes; ++ps) {
-        int shift = 8 * ps;
+        int shift = lo_bit + 8 * ps;
         k_digit_hist<<<nb, kSortThreads, 0, s>>>(kin, n, shift, hist, nb);
         PCMS_HIP(hipGetLastError());
         pcms_status st = scan_exclusive(hist, 256 * nb, scan_scratch, s);
@@ -471,7 +473,8 @@ pcms_status gather_records(Grid *grid, const double *src, hipStream_t s)
 }
 
 pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
-                              double pts_per_cell, hipStream_t s)
+                              double pts_per_cell, hipStream_t s,
+                              const std::function<pcms_status()> *after_params)
 {
     const int n = (int)grid->n_src;
     size_t bytes = grid_build_scratch_bytes(n);
@@ -496,6 +499,7 @@ pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
 
     if ((st = source_bbox_params(grid, src, gdev, bb, cell_width, pts_per_cell, s)) != PCMS_OK)
         return st;
+    if (after_params && (st = (*after_params)()) != PCMS_OK) return st;
     if ((st = bucket_keys(grid->dim, grid->params, src, n, k0, grid->perm, grid_blocks(n, 256), s)) != PCMS_OK)
         return st;
     st = radix_sort(k0, grid->perm, k1, v1, n, key_bits(grid->n_cells_cap), hist, scan_scratch, s);
@@ -555,10 +559,21 @@ pcms_status sort_targets(const Grid *grid, const double *tgt, int64_t n_tgt, int
             return st;
         bits = key_bits(grid->n_cells_cap);
     }
-    st = radix_sort(k0, tperm, k1, v1, n, bits, hist, scan_scratch, s);
+    // only the key's top target_key_bits() bits are sorted on: the order is
+    // for locality (a wave's targets close together), and the lowest bits
+    // of the finest keys buy no measurable locality for their extra pass
+    st = radix_sort(k0, tperm, k1, v1, n, bits, hist, scan_scratch, s,
+                    std::max(bits - target_key_bits(), 0));
     if (st != PCMS_OK) return st;
     if (raw) scratch_free(raw, s);
     return PCMS_OK;
+}
+
+int target_key_bits()
+{
+    const char *env = getenv("PCMS_TARGET_KEY_BITS");
+    const int v = env ? atoi(env) : 0;
+    return v >= 8 && v <= 32 ? v : kTargetKeyBits;
 }
 
 pcms_status sort_pairs(unsigned *k0, int *v0, unsigned *k1, int *v1, int n, int bits, int *hist,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -52,8 +53,11 @@ void scratch_free(void *p, hipStream_t s);
 int cells_cap_for(int64_t n_src);
 // Builds `grid` (allocated by the caller with the right capacity) from src.
 // cell_width > 0: metric bucket width; else buckets sized for pts_per_cell.
+// after_params (may be NULL) is called once grid->params is enqueued, before
+// the sort: work that needs only the parameters can fork off there.
 pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
-                              double pts_per_cell, hipStream_t s);
+                              double pts_per_cell, hipStream_t s,
+                              const std::function<pcms_status()> *after_params = nullptr);
 // Stream-ordered scratch that build_grid_device takes while it runs.
 size_t grid_build_scratch_bytes(int64_t n_src);
 // The two stages build_grid_device shares with the LBVH build: the bounding
@@ -65,7 +69,8 @@ pcms_status source_bbox_params(Grid *grid, const double *src, double *gdev, long
 pcms_status gather_records(Grid *grid, const double *src, hipStream_t s);
 // LBVH over the sources (lbvh.hip): `grid` allocated with n_cells_cap = 1
 // and bvh_node_bytes() of records; leaves of at most max_leaf sources.
-pcms_status build_lbvh_device(Grid *grid, const double *src, int max_leaf, hipStream_t s);
+pcms_status build_lbvh_device(Grid *grid, const double *src, int max_leaf, hipStream_t s,
+                              const std::function<pcms_status()> *after_params = nullptr);
 size_t bvh_node_bytes(int64_t n_src, int dim);
 size_t bvh_link_ints(int64_t n_src);   // build scratch of the tree passes
 // Exclusive scan of n ints in place; scratch holds exclusive_scan_ints(n).
@@ -74,6 +79,12 @@ size_t exclusive_scan_ints(int n);
 // 32-bit Morton codes of points in the box of gp (keys) with their indices.
 pcms_status morton_keys(int dim, const GridParams *gp, const double *pts, int64_t n,
                         unsigned *keys, int *vals, hipStream_t s);
+// Bits of the target ordering key that the sort uses (the top ones): 24, or
+// PCMS_TARGET_KEY_BITS (8..32) from the environment.  Fewer bits save sort
+// passes but cost more in the search kernel than they save (16 bits: the
+// 4M-target kNN step's kernel takes 13 % longer).
+constexpr int kTargetKeyBits = 24;
+int target_key_bits();
 // Target ordering: tperm[i] = index of the target at sorted position i.  Its
 // sort buffers are `ws` (sort_targets_bytes(n_tgt) bytes, 256-byte aligned)
 // when given, else stream-ordered scratch.
@@ -101,14 +112,25 @@ int bits_for(double bound);
 // Bytes of the workspace of transfer_on_grid: status counts, target order,
 // its sort buffers and the bucket-ordered field records.
 size_t transfer_ws_bytes(int64_t n_src, int n_fields, int64_t n_tgt);
+// The target order's part of that workspace: tperm and its sort buffers.
+void transfer_ws_order(void *ws, int64_t n_src, int n_fields, int64_t n_tgt, int **tperm,
+                       void **sort_ws);
+// Target ordering of grid g on the calling thread's side stream (default
+// priority, created once per device), after the work enqueued so far on s;
+// *join is recorded there when tperm is complete, for s to wait on.
+pcms_status order_targets_aside(const Grid *g, const double *tgt, int64_t n_tgt, int *tperm,
+                                void *sort_ws, hipStream_t s, hipEvent_t *join);
 // Target ordering, field gather, search-and-fit and the status plumbing of
 // a transfer on grid g (arguments already validated).  ws: a device
 // workspace of transfer_ws_bytes(...) bytes, 256-byte aligned, or NULL for
-// stream-ordered scratch.
+// stream-ordered scratch.  overlap: order the targets on the side stream
+// while the fields are gathered on s.  ordered: the target order is already
+// being computed into ws (order_targets_aside), complete at this event.
 pcms_status transfer_on_grid(const Grid *g, const double *src_vals, int32_t n_fields,
                              const double *tgt, int64_t n_tgt, int32_t degree,
                              const pcms_radius *radius, int32_t k_cap, const pcms_mls_opts *opts,
-                             hipStream_t s, double *tgt_vals, uint8_t *status, void *ws);
+                             hipStream_t s, double *tgt_vals, uint8_t *status, void *ws,
+                             bool overlap = false, hipEvent_t ordered = nullptr);
 // Turns off the calling thread's phase timing for the next transfer.
 void profile_off();
 // Host-side validation of a transfer's arguments (PCMS_ERR_ARG with a message).

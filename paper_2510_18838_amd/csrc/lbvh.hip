@@ -313,7 +313,8 @@ pcms_status morton_keys(int dim, const GridParams *gp, const double *pts, int64_
     return PCMS_OK;
 }
 
-pcms_status build_lbvh_device(Grid *g, const double *src, int max_leaf, hipStream_t s)
+pcms_status build_lbvh_device(Grid *g, const double *src, int max_leaf, hipStream_t s,
+                              const std::function<pcms_status()> *after_params)
 {
     const int dim = g->dim;
     const int n = (int)g->n_src;
@@ -339,8 +340,10 @@ pcms_status build_lbvh_device(Grid *g, const double *src, int max_leaf, hipStrea
     cur += sizeof(int) * sort_scan_ints(n);
     cur = (char *)(((uintptr_t)cur + 255) & ~(uintptr_t)255);
     const TreeScratch w((int *)cur, n);
+    g->lbvh = 1;   // before after_params: work forked there orders targets by Morton code
 
     if ((st = source_bbox_params(g, src, gdev, bb, 0.0, (double)n, s)) != PCMS_OK) return st;
+    if (after_params && (st = (*after_params)()) != PCMS_OK) return st;
     if ((st = morton_keys(dim, g->params, src, n, k0, g->perm, s)) != PCMS_OK) return st;
     if ((st = sort_pairs(k0, g->perm, k1, v1, n, 32, hist, scan_scratch, s)) != PCMS_OK) return st;
     k_single_cell<<<1, 64, 0, s>>>(n, g->cell_start);
@@ -356,7 +359,6 @@ pcms_status build_lbvh_device(Grid *g, const double *src, int max_leaf, hipStrea
     default: st = build_tree<5>(g, k0, n, max_leaf, cut, lid, w, s); break;
     }
     if (st != PCMS_OK) return st;
-    g->lbvh = 1;
     scratch_free(raw, s);
     return PCMS_OK;
 }

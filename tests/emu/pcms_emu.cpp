@@ -316,6 +316,11 @@ int main(int argc, char **argv)
             while (tbits < 32 && (double)(1ull << tbits) < bound) ++tbits;
         }
     }
+    // the library sorts on the key's top 24 bits only
+    if (tbits > 24) {
+        for (auto &k : tkeys) k >>= (tbits - 24);
+        tbits = 24;
+    }
     radix_sort_emu(tkeys, tperm, tbits);
     const int nfs = padded_dim((int)nf);
     std::vector<double> svals((size_t)(n_src * nfs), 0.0);
