@@ -41,6 +41,10 @@ struct BArgs {
 template <int PREC>
 pcms_status batch_launch(int cls, const BArgs &b, int block, size_t shm, hipStream_t s);
 
+#ifndef PCMS_BATCH_WAVES
+#define PCMS_BATCH_WAVES(PREC) ((PREC) == PCMS_MIXED_REFINE ? 2 : 3)
+#endif
+
 namespace {
 
 // Transfer of one class of problems (dimension D, degree P, metric UNIT):
@@ -53,7 +57,7 @@ namespace {
 // kept the per-target state of one item live across the loop and spilled
 // 200-290 bytes per lane.)
 template <int PREC, int D, int P, bool UNIT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PCMS_BATCH_WAVES(PREC))))
 k_batch_transfer(BArgs b)
 {
     extern __shared__ int lds[];
