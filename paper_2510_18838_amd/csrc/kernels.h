@@ -58,15 +58,18 @@ __global__ void __launch_bounds__(256) k_neighbors(KArgs a)
     add_summary(a.summary, st, active && g.q == 0);
 }
 
-// Waves per SIMD the register allocator targets (168 VGPRs for 3).
-#ifndef PCMS_WAVES_REFINE
-#define PCMS_WAVES_REFINE 3
-#endif
-template <int PREC>
-constexpr int waves_for() { return PREC == PCMS_MIXED_REFINE ? PCMS_WAVES_REFINE : 3; }
+// Waves per SIMD the register allocator targets (168 VGPRs for 3, 256 for
+// 2).  Three, except for the 5-D MIXED_REFINE kernels, which spill 240
+// bytes per lane under 168 VGPRs: at two they do not, and the 2M-target 5-D
+// linear transfer's kernel went from 3-6 % slower than FP64 to level with
+// it (74.3 against 76.1 ms, means of three runs); the 3-D quadratic kernel
+// loses a quarter of its speed at two (7.0 -> 9.2 ms), its latency needs
+// the third wave.
+template <int PREC, int D>
+constexpr int waves_for() { return PREC == PCMS_MIXED_REFINE && D >= 5 ? 2 : 3; }
 
 template <int D, int P, int PREC, bool UNIT, int G, bool BVH = false>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for<PREC>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for<PREC, D>())))
 k_transfer(KArgs a)
 {
     extern __shared__ int lds[];
@@ -86,7 +89,7 @@ k_transfer(KArgs a)
 
 // The same kernel writing the transfer operator instead of field values.
 template <int D, int P, int PREC, bool UNIT, int G, bool BVH = false>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for<PREC>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for<PREC, D>())))
 k_operator(KArgs a)
 {
     extern __shared__ int lds[];
