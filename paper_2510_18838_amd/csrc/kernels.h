@@ -59,17 +59,23 @@ __global__ void __launch_bounds__(256) k_neighbors(KArgs a)
 }
 
 // Waves per SIMD the register allocator targets (168 VGPRs for 3, 256 for
-// 2).  Three, except for the 5-D MIXED_REFINE kernels, which spill 240
-// bytes per lane under 168 VGPRs: at two they do not, and the 2M-target 5-D
-// linear transfer's kernel went from 3-6 % slower than FP64 to level with
-// it (74.3 against 76.1 ms, means of three runs); the 3-D quadratic kernel
-// loses a quarter of its speed at two (7.0 -> 9.2 ms), its latency needs
-// the third wave.
-template <int PREC, int D>
-constexpr int waves_for() { return PREC == PCMS_MIXED_REFINE && D >= 5 ? 2 : 3; }
+// 2): three, except for MIXED_REFINE in 4-D and 5-D (240-1100 bytes of
+// spill per lane under 168 VGPRs) and the 4-D and 5-D quadratic bases in
+// any precision (1-2 KB), which get two.  Measured: the 5-D linear
+// MIXED_REFINE kernel went from 3-6 % slower than FP64 to level with it
+// (74.3 against 76.1 ms, means of three runs).  The low-dimensional
+// kernels need the third wave for latency even where they spill a little:
+// at two, the 3-D quadratic MIXED_REFINE kernel (52 bytes of spill) slows
+// from 7.0 to 9.2 ms and the 2-D quadratic one (132 bytes) from 0.43 to
+// 0.48 ms.
+template <int PREC, int D, int P>
+constexpr int waves_for()
+{
+    return D >= 4 && (PREC == PCMS_MIXED_REFINE || P == 2) ? 2 : 3;
+}
 
 template <int D, int P, int PREC, bool UNIT, int G, bool BVH = false>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for<PREC, D>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for<PREC, D, P>())))
 k_transfer(KArgs a)
 {
     extern __shared__ int lds[];
@@ -89,7 +95,7 @@ k_transfer(KArgs a)
 
 // The same kernel writing the transfer operator instead of field values.
 template <int D, int P, int PREC, bool UNIT, int G, bool BVH = false>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for<PREC, D>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for<PREC, D, P>())))
 k_operator(KArgs a)
 {
     extern __shared__ int lds[];
