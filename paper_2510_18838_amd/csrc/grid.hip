@@ -193,6 +193,14 @@ k_digit_hist(const unsigned *__restrict__ keys, int n, int shift, int *__restric
     hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];   // digit-major
 }
 
+// One block's kSortItems keys: each is ranked within its digit in block
+// order (the wave multisplit of every round against the block's running
+// digit counts), placed digit-sorted in LDS, and then written out so that
+// consecutive threads store consecutive slots of one digit's run (the run
+// starts at the block's global offset for the digit).  Writing straight
+// from the rounds stored every key to an isolated slot; the reorder makes
+// the stores whole segments.  Stable: a digit's keys keep their block order,
+// and the blocks their order through the digit-major offsets.
 __global__ void __launch_bounds__(kSortThreads)
 k_digit_scatter(const unsigned *__restrict__ kin, const int *__restrict__ vin, int n, int shift,
                 const int *__restrict__ offs, int nb, unsigned *__restrict__ kout,
@@ -200,18 +208,27 @@ k_digit_scatter(const unsigned *__restrict__ kin, const int *__restrict__ vin, i
 {
     __shared__ int running[256];
     __shared__ int wave_cnt[4][256];
+    __shared__ int lstart[257];
+    __shared__ unsigned skey[kSortItems];
+    __shared__ int sval[kSortItems];
     const int t = threadIdx.x;
     const int w = t >> 6;
     const int lane = t & 63;
-    running[t] = offs[t * nb + blockIdx.x];
-    int base = blockIdx.x * kSortItems;
+    running[t] = 0;
+    const int base = blockIdx.x * kSortItems;
+    unsigned key_r[kSortRounds];
+    int val_r[kSortRounds], lpos_r[kSortRounds];
+#pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        if (base + r * kSortThreads >= n) break;      // uniform across the block
-        int i = base + r * kSortThreads + t;
-        bool valid = i < n;
-        unsigned key = valid ? kin[i] : 0u;
-        int val = valid ? vin[i] : 0;
-        int digit = (key >> shift) & 255;
+        lpos_r[r] = -1;
+        key_r[r] = 0u;
+        val_r[r] = 0;
+        if (base + r * kSortThreads >= n) continue;      // uniform across the block
+        const int i = base + r * kSortThreads + t;
+        const bool valid = i < n;
+        const unsigned key = valid ? kin[i] : 0u;
+        const int val = valid ? vin[i] : 0;
+        const int digit = (key >> shift) & 255;
         unsigned long long bits[8];
 #pragma unroll
         for (int b = 0; b < 8; ++b) bits[b] = __ballot((digit >> b) & 1);
@@ -224,13 +241,41 @@ k_digit_scatter(const unsigned *__restrict__ kin, const int *__restrict__ vin, i
         if (valid && (mask & lanes_below(lane)) == 0) wave_cnt[w][digit] = __popcll(mask);
         __syncthreads();
         if (valid) {
-            int pos = scatter_slot(running[digit], wave_cnt, w, digit, mask, lane);
-            kout[pos] = key;
-            vout[pos] = val;
+            lpos_r[r] = scatter_slot(running[digit], wave_cnt, w, digit, mask, lane);
+            key_r[r] = key;
+            val_r[r] = val;
         }
         __syncthreads();
         running[t] += wave_cnt[0][t] + wave_cnt[1][t] + wave_cnt[2][t] + wave_cnt[3][t];
         __syncthreads();
+    }
+    // lstart = exclusive scan of the block's digit counts (Hillis-Steele)
+    int c = running[t];
+    lstart[t + 1] = c;
+    if (t == 0) lstart[0] = 0;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int x = t >= off ? lstart[t + 1 - off] : 0;
+        __syncthreads();
+        lstart[t + 1] += x;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        if (lpos_r[r] >= 0) {
+            const int p = lstart[(key_r[r] >> shift) & 255] + lpos_r[r];
+            skey[p] = key_r[r];
+            sval[p] = val_r[r];
+        }
+    }
+    __syncthreads();
+    const int nvalid = min(kSortItems, n - base);
+    for (int j = t; j < nvalid; j += kSortThreads) {
+        const unsigned key = skey[j];
+        const int d = (key >> shift) & 255;
+        const int pos = offs[d * nb + blockIdx.x] + (j - lstart[d]);
+        kout[pos] = key;
+        vout[pos] = sval[j];
     }
 }
 
