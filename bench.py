@@ -476,7 +476,7 @@ def main():
     ap.add_argument("--no-operator", action="store_true",
                     help="skip the precomputed-operator leg")
     ap.add_argument("--no-batch", action="store_true",
-                    help="skip the batched leg (512 uneven problems in one persistent launch)")
+                    help="skip the batched leg (512 uneven problems, one graph replay)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other single-GPU workloads (2-D lattice, 5-D, small 2-D)")
     ap.add_argument("--no-lbvh", action="store_true",

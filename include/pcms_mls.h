@@ -25,7 +25,14 @@
  *    int32 (n_src < 2^31).  Coordinates must be finite.
  *  - Every call enqueues on `stream` (NULL = the null stream).  Unless
  *    PCMS_ASYNC is set, the call then waits for the stream and turns the
- *    per-target statuses into its return code.
+ *    per-target statuses into its return code.  The transfers without
+ *    PCMS_PROFILE (pcms_mls_transfer, pcms_mls_transfer_grid) also run the
+ *    target ordering on a library-owned side stream of the calling thread
+ *    (one per device, default priority), forked from `stream` with an event
+ *    and joined back before the work that reads it, so everything the call
+ *    enqueues stays ordered after earlier work on `stream` and before later
+ *    work (a HIP graph capture of `stream` takes the side stream's work in
+ *    through the event).
  *  - Argument errors are detected on the host before any HIP call and
  *    return PCMS_ERR_ARG.  No C++ exception crosses this interface.  The
  *    last error message of the calling thread is pcms_last_error().
@@ -260,8 +267,8 @@ pcms_status pcms_operator_free(pcms_operator *op);
 /* ---------------------------------------------------------------------- */
 /* Batched transfer: many independent problems of uneven size, dimension,  */
 /* degree and field count (each one the operation of pcms_mls_transfer)    */
-/* executed from one work queue, largest items first, with every stage     */
-/* captured once into a HIP graph and replayed.                            */
+/* executed as work items grouped by class, largest first, with every      */
+/* stage captured once into a HIP graph and replayed.                      */
 /* ---------------------------------------------------------------------- */
 
 /* One problem of a batch.  Every pointer is a DEVICE pointer except
@@ -322,8 +329,9 @@ pcms_status pcms_batch_plan_create(const pcms_problem *problems, int32_t n,
  * one-problem kernel after them).  The first
  * call on a plan with a non-null stream captures the sequence into a HIP
  * graph and later calls replay it (the legacy null stream cannot be
- * captured: there every call enqueues the kernels directly).  summary: DEVICE int32[4] or NULL.  With summary NULL the call waits
- * and returns the batch's status code as pcms_mls_transfer does; with a
+ * captured: there every call enqueues the kernels directly).  summary:
+ * DEVICE int32[4] or NULL.  With summary NULL the call waits and returns
+ * the batch's status code as pcms_mls_transfer does; with a
  * summary it returns after enqueue and the counts of statuses 1, 2, 3 and
  * CAPPED over all problems land there.  Calls on one plan must not overlap. */
 pcms_status pcms_batch_plan_exec(pcms_batch_plan *plan, pcms_stream_t stream, int32_t *summary);
