@@ -31,8 +31,9 @@
  *    (one per device, default priority), forked from `stream` with an event
  *    and joined back before the work that reads it, so everything the call
  *    enqueues stays ordered after earlier work on `stream` and before later
- *    work (a HIP graph capture of `stream` takes the side stream's work in
- *    through the event).
+ *    work.  For HIP graph capture use pcms_mls_transfer_grid_noalloc (no
+ *    allocation, no side stream, no host-to-device copy) or a batch plan,
+ *    which captures itself.
  *  - Argument errors are detected on the host before any HIP call and
  *    return PCMS_ERR_ARG.  No C++ exception crosses this interface.  The
  *    last error message of the calling thread is pcms_last_error().
