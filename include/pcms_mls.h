@@ -156,7 +156,14 @@ typedef struct pcms_grid pcms_grid;
  * of the coordinates, so `src` may be freed once the stream has passed this
  * call.  inv_scale: HOST float64[dim] metric factors g (NULL = all 1).
  * cell_width: bucket width in metric units (> 0), or 0 to size buckets for
- * about `pts_per_cell` sources each (pts_per_cell <= 0 picks 2^dim).
+ * about `pts_per_cell` sources each (pts_per_cell <= 0 picks 2^dim).  In
+ * two or more dimensions, dimension 0 (along which a row of buckets is
+ * contiguous in sorted order) is then cut into 4 slices per bucket width,
+ * or into 1, 2, 8 or 16 if the environment variable PCMS_ROW_SLICES says
+ * so (fewer if the bucket count would exceed 2 n_src + 64; then the width
+ * grows): a search pays per row of buckets, and the slices let each row's
+ * range follow the ball's chord.  Every grid the library builds (one-shot
+ * calls, operators, batches) is sliced the same way.
  * Reusable across transfers of changing fields (the paper's case of a static
  * discretisation queried many times). */
 pcms_status pcms_grid_build(const double *src, int64_t n_src, int32_t dim, const double *inv_scale,

@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(256) k_batch_bbox(const BatchProb *__restrict_
 
 // Bucket sizing of every problem (one thread each).
 __global__ void k_batch_params(const BatchProb *__restrict__ probs, int n,
-                               const long long *__restrict__ bb, GridParams *params)
+                               const long long *__restrict__ bb, int sub, GridParams *params)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
@@ -150,7 +150,7 @@ __global__ void k_batch_params(const BatchProb *__restrict__ probs, int n,
         hi[k] = k < P.dim ? ordered_val(bb[(size_t)q * 2 * kMaxDim + kMaxDim + k]) : 0.0;
     }
     grid_params_compute(lo, hi, P.dim, P.n_src, P.g, P.cell_width, P.pts_per_cell, P.cells_cap,
-                        &params[q]);
+                        sub, &params[q]);
 }
 
 // Sort keys of all sources: problem key offset + bucket id; value = global
@@ -460,7 +460,7 @@ pcms_status batch_enqueue(BatchPlan &p, hipStream_t s)
     k_batch_bbox<<<grid_for((p.n_src_tot + kChunk - 1) / kChunk, 1), 256, 0, s>>>(p.probs_d, p.src_pref, n,
                                                                                  p.bb);
     PCMS_HIP(hipGetLastError());
-    k_batch_params<<<grid_for(n, 64), 64, 0, s>>>(p.probs_d, n, p.bb, p.params);
+    k_batch_params<<<grid_for(n, 64), 64, 0, s>>>(p.probs_d, n, p.bb, row_slices(), p.params);
     PCMS_HIP(hipGetLastError());
     k_batch_src_keys<<<grid_for(p.n_src_tot, tpb), tpb, 0, s>>>(p.probs_d, p.params, p.src_pref, n,
                                                                p.k0, p.v0);

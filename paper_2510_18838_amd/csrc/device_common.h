@@ -59,14 +59,20 @@ void pcms_emu_sync(EmuGroup *g, int q);
 namespace pcms {
 
 constexpr int kMaxDim = PCMS_MAX_DIM;
+// Slices of dimension 0 per bucket width in the grids the library builds.
+constexpr int kRowSlices = 4;
 constexpr int kMaxKcap = PCMS_MAX_KCAP;
 
 // Device-resident description of a uniform grid.  Bucket coordinates of a
 // point x are c_k = clamp(floor((x_k - lo_k) * inv_w_k), 0, n_k - 1); the
 // linear bucket id is row-major with dimension 0 fastest, so the buckets of
-// one "row" (fixed c_1..c_{d-1}) are contiguous in sorted order.
+// one "row" (fixed c_1..c_{d-1}) are contiguous in sorted order.  Dimension
+// 0 is cut `sub` times finer than the others (w_0 = w / sub in metric
+// units): a search pays per row it visits, not per bucket, so the finer
+// slices narrow each row's range to the ball's chord at no cost in rows.
 struct GridParams {
     int dim;
+    int sub;    // slices of dimension 0 per bucket width (1: cubic buckets)
     int n_cells;
     int n[kMaxDim];
     int stride[kMaxDim];
@@ -88,14 +94,17 @@ PCMS_HD PCMS_INLINE int bucket_of(const GridParams &p, int k, double x)
 }
 
 // Bucket sizing from the bounding box [lo, hi]: width cell_width (metric
-// units) if > 0, else sized for about pts_per_cell sources per bucket; the
-// width grows until the bucket count fits `cap`.
+// units) if > 0, else sized for about pts_per_cell sources per cubic bucket
+// of that width; dimension 0 is then cut into `sub` slices per width (a
+// power of two; 1 in one dimension).  Until the bucket count fits `cap`,
+// sub halves first, then the width grows.
 PCMS_HD inline void grid_params_compute(const double *lo, const double *hi, int dim, int64_t n,
                                         const double *g, double cell_width, double pts_per_cell,
-                                        int cap, GridParams *out)
+                                        int cap, int sub, GridParams *out)
 {
     GridParams p;
     p.dim = dim;
+    p.sub = dim > 1 && sub > 1 ? sub : 1;
     double ext[kMaxDim];
     double vol = 1.0;
     int d_eff = 0;
@@ -143,11 +152,12 @@ PCMS_HD inline void grid_params_compute(const double *lo, const double *hi, int 
     for (int it = 0; it < 4000; ++it) {
         total = 1.0;
         for (int k = 0; k < dim; ++k) {
+            const double wk = k == 0 ? wm / p.sub : wm;
             if (ext[k] > 0.0) {
-                double nk = floor(ext[k] / wm) + 1.0;
+                double nk = floor(ext[k] / wk) + 1.0;
                 nk = fmin(nk, 1073741824.0);
                 p.n[k] = (int)nk;
-                p.w[k] = wm / p.g[k];
+                p.w[k] = wk / p.g[k];
             } else {
                 p.n[k] = 1;
                 p.w[k] = 1.0 / p.g[k];
@@ -156,9 +166,13 @@ PCMS_HD inline void grid_params_compute(const double *lo, const double *hi, int 
             total *= (double)p.n[k];
         }
         if (total <= (double)cap) break;
-        wm *= 1.25;
+        if (p.sub > 1)
+            p.sub /= 2;
+        else
+            wm *= 1.25;
     }
     if (total > (double)cap) {      // never exceed the allocated bucket count
+        p.sub = 1;
         for (int k = 0; k < dim; ++k) {
             p.n[k] = 1;
             p.w[k] = (ext[k] > 0.0 ? 2.0 * ext[k] : 1.0) / p.g[k];
@@ -175,6 +189,16 @@ PCMS_HD inline void grid_params_compute(const double *lo, const double *hi, int 
     *out = p;
 }
 
+// The buckets whose first sorted position is i (0 <= i <= n), from the n
+// sorted bucket keys (each < n_cells): [lo, hi], none when hi < lo.
+// Position 0 starts [0, key[0]], position i (0 < i < n) starts
+// (key[i-1], key[i]] and the end n starts (key[n-1], n_cells].
+PCMS_HD PCMS_INLINE void cell_run(const unsigned *keys, int n, int n_cells, int i, int &lo, int &hi)
+{
+    lo = i == 0 ? 0 : (int)keys[i - 1] + 1;
+    hi = i == n ? n_cells : (int)keys[i];
+}
+
 PCMS_HD PCMS_INLINE unsigned bucket_key(const GridParams &p, const double *x)
 {
     int id = 0;
@@ -182,25 +206,30 @@ PCMS_HD PCMS_INLINE unsigned bucket_key(const GridParams &p, const double *x)
     return (unsigned)id;
 }
 
-// Processing order of the targets: tiles of 8 buckets per side (in every
-// dimension with at least 16 buckets) in row-major order, and Morton order
-// of the buckets inside a tile, so that a wave's consecutive targets cover a
-// compact block of buckets.  Keys are below tile_key_bound(n_cells, dim).
+// Processing order of the targets: tiles of 8 cubic buckets per side (the
+// slices of dimension 0 merged; tiled in every dimension with at least 16
+// such buckets) in row-major order, and Morton order of the buckets inside
+// a tile, so that a wave's consecutive targets cover a compact block of
+// buckets.  Keys are below tile_key_bound(n_cells, dim).
 PCMS_HD PCMS_INLINE unsigned target_key(const GridParams &p, const double *x)
 {
     unsigned tile = 0, tstride = 1, local = 0;
     int nt = 0;   // tiled dimensions so far
     int tiled[kMaxDim], c[kMaxDim];
+    int nk[kMaxDim];
     for (int k = 0; k < p.dim; ++k) {
-        c[k] = bucket_of(p, k, x[k]);
-        tiled[k] = p.n[k] >= 16;
+        // the slices of dimension 0 are merged back into cubic buckets
+        const int s = k == 0 ? p.sub : 1;
+        c[k] = bucket_of(p, k, x[k]) / s;
+        nk[k] = (p.n[k] + s - 1) / s;
+        tiled[k] = nk[k] >= 16;
         nt += tiled[k];
     }
     int r = 0;
     for (int k = 0; k < p.dim; ++k) {
         const int sh = tiled[k] ? 3 : 0;
         tile += (unsigned)(c[k] >> sh) * tstride;
-        tstride *= (unsigned)((p.n[k] + (1 << sh) - 1) >> sh);
+        tstride *= (unsigned)((nk[k] + (1 << sh) - 1) >> sh);
         if (tiled[k]) {
             for (int b = 0; b < 3; ++b) local |= (unsigned)((c[k] >> b) & 1) << (b * nt + r);
             ++r;

@@ -98,7 +98,8 @@ __global__ void __launch_bounds__(256) k_bbox(const double *__restrict__ pts, in
 
 // Chooses the bucket widths (one thread).
 __global__ void k_grid_params(const long long *bb, int dim, int64_t n, const double *g,
-                              double cell_width, double pts_per_cell, int cap, GridParams *gp)
+                              double cell_width, double pts_per_cell, int cap, int sub,
+                              GridParams *gp)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double lo[kMaxDim], hi[kMaxDim];
@@ -106,7 +107,7 @@ __global__ void k_grid_params(const long long *bb, int dim, int64_t n, const dou
         lo[k] = ordered_val(bb[k]);
         hi[k] = ordered_val(bb[dim + k]);
     }
-    grid_params_compute(lo, hi, dim, n, g, cell_width, pts_per_cell, cap, gp);
+    grid_params_compute(lo, hi, dim, n, g, cell_width, pts_per_cell, cap, sub, gp);
 }
 
 template <int D>
@@ -383,20 +384,43 @@ size_t sort_scratch_bytes(int n)
     return sizeof(unsigned) * 2 * (size_t)n + sizeof(int) * 2 * (size_t)n + sizeof(int) * ints + 256;
 }
 
-// cell_start[c] = first sorted position whose key is >= c, for c in [0, n_cells].
-__global__ void k_cell_start(const GridParams *__restrict__ gp, const unsigned *__restrict__ keys,
-                             int n, int *__restrict__ cell_start)
+// cell_start[c] = first sorted position whose key is >= c, for c in
+// [0, n_cells], in one pass over the sorted keys: each position i in 0..n
+// writes the buckets it starts (cell_run).  A run of empty buckets
+// shorter than kCellRun is written by the lane that ends it; longer runs are
+// queued in LDS and written by the whole block, so that a large empty region
+// costs a block's coalesced stores instead of one lane's.  One lane per
+// position 0..n, no grid-stride (the queue is per block).
+constexpr int kCellRun = 32;
+constexpr int kCellStartBlock = 256;
+
+__global__ void __launch_bounds__(kCellStartBlock)
+k_cell_start(const GridParams *__restrict__ gp, const unsigned *__restrict__ keys, int n,
+             int *__restrict__ cell_start)
 {
-    int n_cells = gp->n_cells;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c <= n_cells; c += gridDim.x * blockDim.x) {
-        int lo = 0, hi = n;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (keys[mid] < (unsigned)c) lo = mid + 1;
-            else hi = mid;
+    __shared__ int q_lo[kCellStartBlock], q_hi[kCellStartBlock], q_val[kCellStartBlock];
+    __shared__ int q_n;
+    const int n_cells = gp->n_cells;
+    if (threadIdx.x == 0) q_n = 0;
+    __syncthreads();
+    const int i = (int)blockIdx.x * kCellStartBlock + (int)threadIdx.x;
+    if (i <= n) {
+        int lo, hi;
+        cell_run(keys, n, n_cells, i, lo, hi);
+        if (hi - lo < kCellRun) {
+            for (int c = lo; c <= hi; ++c) cell_start[c] = i;
+        } else {
+            const int e = atomicAdd(&q_n, 1);
+            q_lo[e] = lo;
+            q_hi[e] = hi;
+            q_val[e] = i;
         }
-        cell_start[c] = lo;
     }
+    __syncthreads();
+    const int m = q_n;
+    for (int e = 0; e < m; ++e)
+        for (int c = q_lo[e] + (int)threadIdx.x; c <= q_hi[e]; c += kCellStartBlock)
+            cell_start[c] = q_val[e];
 }
 
 // Sorted coordinates with the padded stride (padding written as zero), their
@@ -472,6 +496,13 @@ int grid_blocks(int64_t n, int tpb)
 
 }  // namespace
 
+int row_slices()
+{
+    const char *env = getenv("PCMS_ROW_SLICES");
+    const int v = env ? atoi(env) : 0;
+    return v == 1 || v == 2 || v == 4 || v == 8 || v == 16 ? v : kRowSlices;
+}
+
 int cells_cap_for(int64_t n_src)
 {
     int64_t c = 2 * n_src + 64;
@@ -495,7 +526,7 @@ pcms_status source_bbox_params(Grid *grid, const double *src, double *gdev, long
     pcms_status st = bbox(dim, src, n, bb, s);
     if (st != PCMS_OK) return st;
     k_grid_params<<<1, 1, 0, s>>>(bb, dim, n, gdev, cell_width, pts_per_cell, grid->n_cells_cap,
-                                  grid->params);
+                                  row_slices(), grid->params);
     PCMS_HIP(hipGetLastError());
     return PCMS_OK;
 }
@@ -549,8 +580,8 @@ pcms_status build_grid_device(Grid *grid, const double *src, double cell_width,
         return st;
     st = radix_sort(k0, grid->perm, k1, v1, n, key_bits(grid->n_cells_cap), hist, scan_scratch, s);
     if (st != PCMS_OK) return st;
-    k_cell_start<<<grid_blocks((int64_t)grid->n_cells_cap + 1, 256), 256, 0, s>>>(
-        grid->params, k0, n, grid->cell_start);
+    k_cell_start<<<(unsigned)(((int64_t)n + kCellStartBlock) / kCellStartBlock), kCellStartBlock, 0,
+                   s>>>(grid->params, k0, n, grid->cell_start);
     PCMS_HIP(hipGetLastError());
     if ((st = gather_records(grid, src, s)) != PCMS_OK) return st;
     scratch_free(raw, s);

@@ -51,6 +51,9 @@ void scratch_free(void *p, hipStream_t s);
 
 // grid construction (sort.hip) ----------------------------------------------
 int cells_cap_for(int64_t n_src);
+// Slices of dimension 0 per bucket width (kRowSlices; the environment
+// variable PCMS_ROW_SLICES = 1, 2, 4, 8 or 16 overrides it).
+int row_slices();
 // Builds `grid` (allocated by the caller with the right capacity) from src.
 // cell_width > 0: metric bucket width; else buckets sized for pts_per_cell.
 // after_params (may be NULL) is called once grid->params is enqueued, before

@@ -432,7 +432,8 @@ struct Search {
     }
 
     // Radius of a ball expected to hold k sources, from the bucket counts
-    // around t (no point loads).
+    // around t (no point loads): the 3^d block of bucket widths around t's
+    // bucket, which in dimension 0 spans sub + sub/2 slices to each side.
     PCMS_HD double knn_radius_guess(int k) const
     {
         if constexpr (BVH) return bvh_radius_guess<D, UNIT>(gp, bv, t, k);
@@ -440,9 +441,10 @@ struct Search {
         double vol = 1.0;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
+            const int h = j == 0 ? gp.sub + gp.sub / 2 : 1;
             int cj = bucket_of(gp, j, t[j]);
-            a[j] = max(cj - 1, 0);
-            b[j] = min(cj + 1, gp.n[j] - 1);
+            a[j] = max(cj - h, 0);
+            b[j] = min(cj + h, gp.n[j] - 1);
             c[j] = a[j];
             vol *= (double)(b[j] - a[j] + 1) * gp.w[j] * gp.g[j];
         }

@@ -199,6 +199,9 @@ int main(int argc, char **argv)
     const int n_min = (int)rd.i64(), max_iter = (int)rd.i64(), k_cap = (int)rd.i64();
     const int weight = (int)rd.i64(), precision = (int)rd.i64(), group = (int)rd.i64();
     const double r = rd.f64(), lambda = rd.f64(), cell_width = rd.f64(), ppc = rd.f64();
+    // slices of dimension 0 per bucket width, as the library's grids take them
+    const char *env_sub = std::getenv("PCMS_ROW_SLICES");
+    const int row_slices = env_sub ? std::atoi(env_sub) : kRowSlices;
     double g[kMaxDim];
     for (int q = 0; q < kMaxDim; ++q) g[q] = rd.f64();
     auto src = rd.arr<double>((size_t)(n_src * dim));
@@ -220,9 +223,9 @@ int main(int argc, char **argv)
     const int cap = lbvh ? 1 : (int)std::min<int64_t>(2 * n_src + 64, (int64_t)1 << 30);
     GridParams gp;
     if (lbvh)
-        grid_params_compute(lo, hi, (int)dim, n_src, g, 0.0, (double)n_src, 1, &gp);
+        grid_params_compute(lo, hi, (int)dim, n_src, g, 0.0, (double)n_src, 1, 1, &gp);
     else
-        grid_params_compute(lo, hi, (int)dim, n_src, g, cell_width, ppc, cap, &gp);
+        grid_params_compute(lo, hi, (int)dim, n_src, g, cell_width, ppc, cap, row_slices, &gp);
     if (gp.n_cells > cap) die("bucket count above the allocation");
     std::vector<unsigned> keys(n_src);
     std::vector<int> perm(n_src);
@@ -258,6 +261,20 @@ int main(int argc, char **argv)
             else h = mid;
         }
         cs[c] = l;
+    }
+    // the device's one-pass bucket offsets (cell_run) must give the same
+    if (!lbvh) {
+        std::vector<int> cs_runs((size_t)gp.n_cells + 1, -1);
+        for (int i = 0; i <= (int)n_src; ++i) {
+            int lo, hi;
+            cell_run(keys.data(), (int)n_src, gp.n_cells, i, lo, hi);
+            for (int c = lo; c <= hi; ++c) {
+                if (c < 0 || c > gp.n_cells || cs_runs[c] != -1) die("bucket runs overlap");
+                cs_runs[c] = i;
+            }
+        }
+        for (int c = 0; c <= gp.n_cells; ++c)
+            if (cs_runs[c] != cs[c]) die("one-pass bucket offsets differ from the binary search");
     }
     // the kernels may read only [0, n_cells]: keep exactly that for the sanitiser
     cs = std::vector<int>(cs.begin(), cs.begin() + gp.n_cells + 1);

@@ -46,6 +46,15 @@ def test_emu_scaled(name):
     C.case_scaled(BE, name, small=True)
 
 
+@pytest.mark.parametrize("sub", [1, 2, 8, 16])
+def test_emu_row_slices(sub, monkeypatch):
+    """Grids with dimension 0 cut into 1-16 slices per bucket width (the
+    library's default is 4): the same lists and values, in 2-D and 3-D."""
+    monkeypatch.setenv("PCMS_ROW_SLICES", str(sub))
+    C.case_scaled(BE, "c3", small=True)
+    C.case_scaled(BE, "c2", small=True)
+
+
 def test_emu_c4():
     C.case_c4(BE, n=6, size_scale=0.02)
 

@@ -35,6 +35,15 @@ def test_scaled(name):
     C.case_scaled(BE, name)
 
 
+@pytest.mark.parametrize("sub", [1, 2, 8, 16])
+def test_row_slices(sub, monkeypatch):
+    """Grids with dimension 0 cut into 1-16 slices per bucket width (the
+    library's default is 4; PCMS_ROW_SLICES overrides it per build)."""
+    monkeypatch.setenv("PCMS_ROW_SLICES", str(sub))
+    C.case_scaled(BE, "c3")
+    C.case_scaled(BE, "c2")
+
+
 def test_c4_problems_scaled():
     C.case_c4(BE)
 
