@@ -77,6 +77,7 @@ struct GridParams {
     int n[kMaxDim];
     int stride[kMaxDim];
     double lo[kMaxDim];
+    double hi[kMaxDim];     // upper corner of the sources' bounding box
     double w[kMaxDim];      // bucket width, raw coordinates
     double inv_w[kMaxDim];  // 1 / w
     double g[kMaxDim];      // metric factors
@@ -110,6 +111,7 @@ PCMS_HD inline void grid_params_compute(const double *lo, const double *hi, int 
     int d_eff = 0;
     for (int k = 0; k < kMaxDim; ++k) {
         p.lo[k] = 0.0;
+        p.hi[k] = 0.0;
         p.g[k] = 1.0;
         p.n[k] = 1;
         p.w[k] = 1.0;
@@ -127,6 +129,7 @@ PCMS_HD inline void grid_params_compute(const double *lo, const double *hi, int 
             h = 0.0;
         }
         p.lo[k] = l;
+        p.hi[k] = h;
         // quantum 2^(E - 32) with 2^E just above the extent: every source of
         // the box maps to an integer in [0, 2^32)
         if (h > l) {

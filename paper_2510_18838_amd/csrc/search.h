@@ -49,6 +49,22 @@ PCMS_HD PCMS_INLINE double metric_d2(const double (&t)[D], const double *__restr
     return acc;
 }
 
+// Fraction of the unit d-ball's volume beyond the hyperplane at distance x
+// (0 <= x <= 1) from its centre: the integral of (1 - s^2)^((d-1)/2) over
+// [x, 1] over its integral over [-1, 1] (d = 1, 2, 3).
+template <int D>
+PCMS_HD PCMS_INLINE double ball_beyond(double x)
+{
+    static_assert(D >= 1 && D <= 3, "closed forms for 1-3 dimensions");
+    auto P = [](double s) {
+        if constexpr (D == 1) return s;
+        else if constexpr (D == 2) return 0.5 * (s * sqrt(fmax(1.0 - s * s, 0.0)) + asin(s));
+        else return s - s * s * s / 3.0;
+    };
+    x = fmin(fmax(x, 0.0), 1.0);
+    return (P(1.0) - P(x)) / (P(1.0) - P(-1.0));
+}
+
 // Rows of a stencil walk: for radius rho around t, yields the rows (bucket
 // coordinates c_1..c_{d-1}) whose slab is within reach, with each row's
 // linear id and the c_0 range of the ball's chord in that slab.
@@ -477,7 +493,28 @@ struct Search {
             for (int j = 0; j < D; ++j) half = fmax(half, 1.5 * gp.w[j] * gp.g[j]);
             return 2.0 * half;
         }
-        return pow((double)k * vol / ((double)count * vball), 1.0 / D);
+        const double g0 = pow((double)k * vol / ((double)count * vball), 1.0 / D);
+        // Every source lies in the bounding box, so the part of the ball
+        // beyond a face holds none: grow the radius until the part inside is
+        // expected to hold k (faces taken one at a time, two fixed-point
+        // steps; a face behind the target cuts nothing here).  In 1-3
+        // dimensions, where knn_select's window is narrowed to match.
+        if constexpr (D > 3) {
+            return g0;
+        } else {
+            double gr = g0;
+            for (int it = 0; it < 2; ++it) {
+                double f = 1.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const double s = (UNIT ? 1.0 : gp.g[j]) / gr;
+                    f *= 1.0 - ball_beyond<D>((t[j] - gp.lo[j]) * s) -
+                         ball_beyond<D>((gp.hi[j] - t[j]) * s);
+                }
+                gr = g0 * pow(f, -1.0 / D);
+            }
+            return gr;
+        }
     }
 
     // Appends the values D in [lo, hi) to the buffer (ordered compaction,
@@ -531,16 +568,18 @@ struct Search {
     }
 
     // kNN selection in two walks, for k <= k_cap + 1: select_window over the
-    // window [((1 - 0.22) g)^2, ((1 + 0.3) g)^2), g the bucket-count estimate
-    // of the radius.  On success r2 is the k-th smallest D, the list holds
+    // window [(a g)^2, (b g)^2), g the estimate of the radius.  With the
+    // grid's estimate in 1-3 dimensions the window is [0.8 g, 1.18 g), else
+    // [0.78 g, 1.3 g).  On success r2 is the k-th smallest D, the list holds
     // every source with D < r2 and n_found their count (< k); false leaves
     // the general path to the caller.
     template <bool F32 = false>
     PCMS_HD bool knn_select(int k, double &r2, int &n_found)
     {
+        constexpr bool kTight = !BVH && D <= 3;
+        constexpr double a = kTight ? 0.8 : 0.78, b = kTight ? 1.18 : 1.3;
         const double gr = knn_radius_guess(k);
-        return select_window<F32, false>(k, (0.78 * gr) * (0.78 * gr), (1.3 * gr) * (1.3 * gr), r2,
-                                         n_found);
+        return select_window<F32, false>(k, (a * gr) * (a * gr), (b * gr) * (b * gr), r2, n_found);
     }
 
     // The k-th smallest D in two walks, given a window [lo, hi) expected to
