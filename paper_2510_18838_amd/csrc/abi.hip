@@ -395,13 +395,22 @@ pcms_status side_stream(Side **out)
 }
 }  // namespace
 
-pcms_status order_targets_aside(const Grid *g, const double *tgt, int64_t n_tgt, int *tperm,
-                                void *sort_ws, hipStream_t s, hipEvent_t *join)
+pcms_status side_fork(hipStream_t s)
 {
     Side *sd = nullptr;
     pcms_status st = side_stream(&sd);
     if (st != PCMS_OK) return st;
     PCMS_HIP(hipEventRecord(sd->fork, s));
+    return PCMS_OK;
+}
+
+pcms_status order_targets_aside(const Grid *g, const double *tgt, int64_t n_tgt, int *tperm,
+                                void *sort_ws, hipStream_t s, hipEvent_t *join, bool record_fork)
+{
+    Side *sd = nullptr;
+    pcms_status st = side_stream(&sd);
+    if (st != PCMS_OK) return st;
+    if (record_fork) PCMS_HIP(hipEventRecord(sd->fork, s));
     PCMS_HIP(hipStreamWaitEvent(sd->s, sd->fork, 0));
     if ((st = sort_targets(g, tgt, n_tgt, tperm, sd->s, sort_ws)) != PCMS_OK) return st;
     PCMS_HIP(hipEventRecord(sd->join, sd->s));
@@ -689,25 +698,29 @@ pcms_status pcms_mls_transfer(const double *src, int64_t n_src, int32_t dim, con
     const GridLayout L(n_src, dim, lbvh);
     if ((st = scratch_alloc(&sc.p, L.bytes, s)) != PCMS_OK) return st;
     L.place(g, sc.p, lbvh);
-    // unprofiled calls order the targets on the side stream as soon as the
-    // grid's parameters exist, overlapping the rest of the build and the
-    // field gather (profiled calls run the phases in line, to time them)
+    // unprofiled calls order the targets on the side stream from the point
+    // where the grid's parameters exist, overlapping the rest of the build
+    // and the field gather (profiled calls run the phases in line, to time
+    // them).  The fork point is marked there, but the side work is enqueued
+    // after the build's, so the build's kernels are not held up behind the
+    // host's launches of the sort.
     hipEvent_t ordered = nullptr;
-    std::function<pcms_status()> fork;
+    std::function<pcms_status()> fork = [&]() { return side_fork(s); };
     if (!g_prof.on) {
         if ((st = scratch_alloc(&xs.p, transfer_ws_bytes(n_src, n_fields, n_tgt), s)) != PCMS_OK)
             return st;
-        fork = [&]() {
-            int *tperm;
-            void *sort_ws;
-            transfer_ws_order(xs.p, n_src, n_fields, n_tgt, &tperm, &sort_ws);
-            return order_targets_aside(&g, tgt, n_tgt, tperm, sort_ws, s, &ordered);
-        };
     }
     const std::function<pcms_status()> *hook = g_prof.on ? nullptr : &fork;
     st = lbvh ? build_lbvh_device(&g, src, lbvh_leaf_default(), s, hook)
               : build_grid_device(&g, src, cw, ppc, s, hook);
     if (st != PCMS_OK) return st;
+    if (!g_prof.on) {
+        int *tperm;
+        void *sort_ws;
+        transfer_ws_order(xs.p, n_src, n_fields, n_tgt, &tperm, &sort_ws);
+        if ((st = order_targets_aside(&g, tgt, n_tgt, tperm, sort_ws, s, &ordered, false)) != PCMS_OK)
+            return st;
+    }
     return transfer_on_grid(&g, src_vals, n_fields, tgt, n_tgt, basis_degree, radius, k_cap, opts,
                             s, tgt_vals, status, xs.p, !g_prof.on, ordered);
 }

@@ -118,11 +118,17 @@ size_t transfer_ws_bytes(int64_t n_src, int n_fields, int64_t n_tgt);
 // The target order's part of that workspace: tperm and its sort buffers.
 void transfer_ws_order(void *ws, int64_t n_src, int n_fields, int64_t n_tgt, int **tperm,
                        void **sort_ws);
-// Target ordering of grid g on the calling thread's side stream (default
-// priority, created once per device), after the work enqueued so far on s;
+// Marks the point of s after which the calling thread's side stream
+// (default priority, created once per device) may run: records its fork
+// event on s.
+pcms_status side_fork(hipStream_t s);
+// Target ordering of grid g on the calling thread's side stream, after the
+// work enqueued so far on s (record_fork) or after the point side_fork last
+// marked on s (!record_fork: the host can enqueue more work on s first);
 // *join is recorded there when tperm is complete, for s to wait on.
 pcms_status order_targets_aside(const Grid *g, const double *tgt, int64_t n_tgt, int *tperm,
-                                void *sort_ws, hipStream_t s, hipEvent_t *join);
+                                void *sort_ws, hipStream_t s, hipEvent_t *join,
+                                bool record_fork = true);
 // Target ordering, field gather, search-and-fit and the status plumbing of
 // a transfer on grid g (arguments already validated).  ws: a device
 // workspace of transfer_ws_bytes(...) bytes, 256-byte aligned, or NULL for
