@@ -452,7 +452,7 @@ struct Search {
     // bucket, which in dimension 0 spans sub + sub/2 slices to each side.
     PCMS_HD double knn_radius_guess(int k) const
     {
-        if constexpr (BVH) return bvh_radius_guess<D, UNIT>(gp, bv, t, k);
+        if constexpr (BVH) return box_corrected(bvh_radius_guess<D, UNIT>(gp, bv, t, k));
         int a[D], b[D], c[D];
         double vol = 1.0;
 #pragma unroll
@@ -493,12 +493,20 @@ struct Search {
             for (int j = 0; j < D; ++j) half = fmax(half, 1.5 * gp.w[j] * gp.g[j]);
             return 2.0 * half;
         }
-        const double g0 = pow((double)k * vol / ((double)count * vball), 1.0 / D);
-        // Every source lies in the bounding box, so the part of the ball
-        // beyond a face holds none: grow the radius until the part inside is
-        // expected to hold k (faces taken one at a time, two fixed-point
-        // steps; a face behind the target cuts nothing here).  In 1-3
-        // dimensions, where knn_select's window is narrowed to match.
+        return box_corrected(pow((double)k * vol / ((double)count * vball), 1.0 / D));
+    }
+
+    // Every source lies in the bounding box, so the part of a ball beyond a
+    // face holds none: the radius g0 expected to hold k sources at the local
+    // density is grown until the part inside the box is expected to hold k
+    // (faces taken one at a time, two fixed-point steps; a face behind the
+    // target cuts nothing here).  Each dimension keeps at least half of the
+    // ball, as at a face: a box thinner than the ball (flat or coincident
+    // sources) holds a lower-dimensional cloud, which this model does not
+    // describe, so the radius grows at most 2x.  In 1-3 dimensions (where
+    // knn_select narrows the grid's window to match).
+    PCMS_HD double box_corrected(double g0) const
+    {
         if constexpr (D > 3) {
             return g0;
         } else {
@@ -508,12 +516,13 @@ struct Search {
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
                     const double s = (UNIT ? 1.0 : gp.g[j]) / gr;
-                    f *= 1.0 - ball_beyond<D>((t[j] - gp.lo[j]) * s) -
-                         ball_beyond<D>((gp.hi[j] - t[j]) * s);
+                    f *= fmax(1.0 - ball_beyond<D>((t[j] - gp.lo[j]) * s) -
+                                  ball_beyond<D>((gp.hi[j] - t[j]) * s),
+                              0.5);
                 }
                 gr = g0 * pow(f, -1.0 / D);
             }
-            return gr;
+            return gr < INFINITY ? gr : g0;
         }
     }
 
@@ -569,10 +578,11 @@ struct Search {
 
     // kNN selection in two walks, for k <= k_cap + 1: select_window over the
     // window [(a g)^2, (b g)^2), g the estimate of the radius.  With the
-    // grid's estimate in 1-3 dimensions the window is [0.8 g, 1.18 g), else
-    // [0.78 g, 1.3 g).  On success r2 is the k-th smallest D, the list holds
-    // every source with D < r2 and n_found their count (< k); false leaves
-    // the general path to the caller.
+    // grid's estimate corrected for the bounding box (1-3 dimensions) the
+    // window is [0.8 g, 1.18 g); else, and for the LBVH's noisier estimate,
+    // [0.78 g, 1.3 g).  On success r2 is the
+    // k-th smallest D, the list holds every source with D < r2 and n_found
+    // their count (< k); false leaves the general path to the caller.
     template <bool F32 = false>
     PCMS_HD bool knn_select(int k, double &r2, int &n_found)
     {
