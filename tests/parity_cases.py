@@ -238,6 +238,39 @@ def case_ties(be):
     check_lists(be, p, "coincident", brute=True)
 
 
+def case_box_boundary(be):
+    """kNN targets where the bounding-box correction of the radius estimate
+    acts: corners, edge and face centres, targets just inside and outside
+    the faces, in 2-D and 3-D, on the grid and (for backends that have it)
+    the LBVH; then a flat 3-D cloud (one coordinate constant) and a thin
+    slab, where the correction is bounded.  Lists and radii bit-exact,
+    values to the usual bars."""
+    rng = np.random.default_rng(29)
+    for d in (2, 3):
+        src = rng.uniform(0, 1, (6000 if d == 3 else 3000, d))
+        corners = np.array(np.meshgrid(*[[0.0, 1.0]] * d, indexing="ij")).reshape(d, -1).T
+        faces = np.concatenate([np.eye(d) * v + 0.5 * (1 - np.eye(d)) for v in (0.0, 1.0)])
+        mids = (corners[:, None, :] + corners[None, :, :]).reshape(-1, d) / 2
+        near = rng.uniform(0, 1, (300, d))
+        axis = rng.integers(0, d, 300)
+        side = rng.integers(0, 2, 300).astype(float)
+        near[np.arange(300), axis] = side + rng.uniform(-0.03, 0.03, 300)
+        tgt = np.concatenate([corners, faces, mids, near, corners * 1.1 - 0.05])
+        vals = np.stack([np.sin(3 * src.sum(1)), src[:, 0] ** 2])
+        for k, deg in ((10, 1), (40, 2)):
+            p = custom(src, vals, tgt, deg, synth.KNN, k=k, k_cap=64)
+            check_lists(be, p, f"box boundary d={d} k={k}")
+            check_transfer(be, p, f"box boundary d={d} k={k}")
+    flat = rng.uniform(0, 1, (2000, 3))
+    flat[:, 2] = 0.5
+    slab = rng.uniform(0, 1, (2000, 3))
+    slab[:, 2] = 0.5 + 1e-3 * slab[:, 2]
+    tgt = np.concatenate([rng.uniform(0, 1, (200, 3)), [[0.5, 0.5, 0.5], [0.0, 0.0, 0.5]]])
+    for name, src in (("flat", flat), ("slab", slab)):
+        p = custom(src, np.sin(4 * src[:, 0]), tgt, 1, synth.KNN, k=12, k_cap=32)
+        check_lists(be, p, f"{name} cloud", brute=True)
+
+
 def case_tight_caps(be):
     p = synth.uniform_problem(41, 3000, 1500, 2, 2, synth.FIXED, n_fields=1, radius=0.08, k_cap=6)
     check_lists(be, p, "k_cap = m")

@@ -55,6 +55,11 @@ def test_emu_row_slices(sub, monkeypatch):
     C.case_scaled(BE, "c2", small=True)
 
 
+def test_emu_box_boundary():
+    C.case_box_boundary(BE)
+    C.case_box_boundary(BV)
+
+
 def test_emu_c4():
     C.case_c4(BE, n=6, size_scale=0.02)
 

@@ -41,6 +41,10 @@ def test_lbvh_dimensions_and_degrees(dim, degree, mode):
     C.case_dims(BV, dim, degree, mode)
 
 
+def test_lbvh_box_boundary():
+    C.case_box_boundary(BV)
+
+
 def test_lbvh_edge_cases():
     C.case_far_targets(BV)
     C.case_singular_exhausted(BV)

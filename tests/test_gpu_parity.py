@@ -44,6 +44,10 @@ def test_row_slices(sub, monkeypatch):
     C.case_scaled(BE, "c2")
 
 
+def test_box_boundary():
+    C.case_box_boundary(BE)
+
+
 def test_c4_problems_scaled():
     C.case_c4(BE)
 
