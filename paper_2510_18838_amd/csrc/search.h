@@ -582,14 +582,32 @@ struct Search {
     // window is [0.8 g, 1.18 g); else, and for the LBVH's noisier estimate,
     // [0.78 g, 1.3 g).  On success r2 is the
     // k-th smallest D, the list holds every source with D < r2 and n_found
-    // their count (< k); false leaves the general path to the caller.
+    // their count (< k).  When the k-th lies outside the window, one more
+    // window beside it is tried, [b g, 1.5 b g) or [0.6 a g, a g), two walks
+    // instead of the general path's bracketing; false leaves the general
+    // path to the caller.
     template <bool F32 = false>
     PCMS_HD bool knn_select(int k, double &r2, int &n_found)
     {
         constexpr bool kTight = !BVH && D <= 3;
         constexpr double a = kTight ? 0.8 : 0.78, b = kTight ? 1.18 : 1.3;
         const double gr = knn_radius_guess(k);
-        return select_window<F32, false>(k, (a * gr) * (a * gr), (b * gr) * (b * gr), r2, n_found);
+        double lo = (a * gr) * (a * gr), hi = (b * gr) * (b * gr);
+        // one call site, so that the selection is inlined once
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            int side = 0;
+            if (select_window<F32, false>(k, lo, hi, r2, n_found, &side)) return true;
+            if (side > 0) {
+                lo = hi;
+                hi = (1.5 * b * gr) * (1.5 * b * gr);
+            } else if (side < 0) {
+                hi = lo;
+                lo = (0.6 * a * gr) * (0.6 * a * gr);
+            } else {
+                return false;
+            }
+        }
+        return false;
     }
 
     // The k-th smallest D in two walks, given a window [lo, hi) expected to
@@ -606,9 +624,11 @@ struct Search {
     // D < v, n their count (< k); with TIES the list is then completed to k
     // entries with sources at D = v, smallest source index first, and n = k.
     // Returns false when the k-th lies outside [lo, hi) or its bin does not
-    // fit the words.
+    // fit the words; then *side (if given) is -1 if the k-th lies below lo,
+    // +1 if at or above hi, 0 otherwise.
     template <bool F32, bool TIES>
-    PCMS_HD bool select_window(int k, double lo, double hi, double &v, int &n_out)
+    PCMS_HD bool select_window(int k, double lo, double hi, double &v, int &n_out,
+                               int *side = nullptr)
     {
         const int nb = words < 64 ? words : 64;
         const double bw = (hi - lo) / nb, ibw = 1.0 / bw;
@@ -637,7 +657,10 @@ struct Search {
             }
         }
         g.sync();   // every lane has read the bins before the list overwrites them
-        if (b < 0 || c_b + n_b > words) return false;
+        if (b < 0 || c_b + n_b > words) {
+            if (side) *side = b >= 0 ? 0 : c_lo >= k ? -1 : 1;
+            return false;
+        }
         // bin entry j sits in word words - n_b + j
         const int base = words - n_b;
         const double rho2 = b == nb - 1 ? hi : fmin(hi, (lo + (double)(b + 1) * bw) * (1.0 + 1e-12));
