@@ -199,9 +199,13 @@ int main(int argc, char **argv)
     const int n_min = (int)rd.i64(), max_iter = (int)rd.i64(), k_cap = (int)rd.i64();
     const int weight = (int)rd.i64(), precision = (int)rd.i64(), group = (int)rd.i64();
     const double r = rd.f64(), lambda = rd.f64(), cell_width = rd.f64(), ppc = rd.f64();
-    // slices of dimension 0 per bucket width, as the library's grids take them
+    // slices of dimension 0 per bucket width, as the library's grids take
+    // them (the same accepted overrides)
     const char *env_sub = std::getenv("PCMS_ROW_SLICES");
-    const int row_slices = env_sub ? std::atoi(env_sub) : kRowSlices;
+    const int sub_env = env_sub ? std::atoi(env_sub) : 0;
+    const int row_slices =
+        sub_env == 1 || sub_env == 2 || sub_env == 4 || sub_env == 8 || sub_env == 16 ? sub_env
+                                                                                      : kRowSlices;
     double g[kMaxDim];
     for (int q = 0; q < kMaxDim; ++q) g[q] = rd.f64();
     auto src = rd.arr<double>((size_t)(n_src * dim));
