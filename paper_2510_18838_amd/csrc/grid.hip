@@ -46,7 +46,11 @@ __global__ void k_bbox_init(long long *bb, int dim)
 }
 
 // Per-dimension min/max of the points: wave reductions, then one atomic per
-// block and dimension.
+// block and dimension.  Each lane takes kBboxUnroll points per step with
+// their loads issued together (the grid is capped at 1024 blocks to bound
+// the atomics, so a lane has several points and one at a time left the loop
+// bound by load latency).
+constexpr int kBboxUnroll = 4;
 template <int D>
 __global__ void __launch_bounds__(256) k_bbox(const double *__restrict__ pts, int64_t n, long long *bb)
 {
@@ -57,14 +61,24 @@ __global__ void __launch_bounds__(256) k_bbox(const double *__restrict__ pts, in
         mn[k] = INFINITY;
         mx[k] = -INFINITY;
     }
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < n;
+         i0 += kBboxUnroll * stride) {
+        double x[kBboxUnroll][D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            double x = pts[i * D + k];
-            mn[k] = fmin(mn[k], x);
-            mx[k] = fmax(mx[k], x);
+        for (int u = 0; u < kBboxUnroll; ++u) {
+            const int64_t i = i0 + u * stride;
+            const int64_t j = i < n ? i : i0;   // i0 < n: a repeat leaves min and max unchanged
+#pragma unroll
+            for (int k = 0; k < D; ++k) x[u][k] = pts[j * D + k];
         }
+#pragma unroll
+        for (int u = 0; u < kBboxUnroll; ++u)
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                mn[k] = fmin(mn[k], x[u][k]);
+                mx[k] = fmax(mx[k], x[u][k]);
+            }
     }
 #pragma unroll
     for (int k = 0; k < D; ++k) {
