@@ -580,12 +580,11 @@ struct Search {
     // window [(a g)^2, (b g)^2), g the estimate of the radius.  With the
     // grid's estimate corrected for the bounding box (1-3 dimensions) the
     // window is [0.8 g, 1.18 g); else, and for the LBVH's noisier estimate,
-    // [0.78 g, 1.3 g).  On success r2 is the
-    // k-th smallest D, the list holds every source with D < r2 and n_found
-    // their count (< k).  When the k-th lies outside the window, one more
-    // window beside it is tried, [b g, 1.5 b g) or [0.6 a g, a g), two walks
-    // instead of the general path's bracketing; false leaves the general
-    // path to the caller.
+    // [0.78 g, 1.3 g).  On success r2 is the k-th smallest D, the list holds
+    // every source with D < r2 and n_found their count (< k).  When the k-th
+    // lies outside the window, one more window beside it is tried,
+    // [b g, 1.5 b g) or [0.6 a g, a g): two walks instead of the general
+    // path's bracketing.  False leaves the general path to the caller.
     template <bool F32 = false>
     PCMS_HD bool knn_select(int k, double &r2, int &n_found)
     {
